@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the C* Pfaffian-sign hot path on one MI355X.
+
+One step = the whole hot path for one gauge field that is already resident
+in HBM: link packing and the clover term (gauge create from device memory),
+then the sign of the Pfaffian over the kappa path (eigenvalue flow of
+Q = g5 D followed with step A, certified crossing counts; Chebyshev-Davidson
+with FP32/BF16-link filter applies and FP64 Rayleigh-Ritz).
+
+Printed: ONE JSON line with the throughput in Dirac applies/s (right-hand
+sides applied by every kernel launch of the step, all precisions), the time
+per step (= seconds per Pfaffian sign over the path), the roofline of the
+dominant kernel measured with HIP events around its launches inside the
+timed region, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(prec: int, nsites2: int, launches: int, rhs: int) -> float:
+    """Minimum HBM bytes of the apply launches (per doubled site, per launch):
+    every input spinor read once, every output written once, links and clover
+    read once per physical site (shared by its conjugate copy):
+      FP64: 384 B per RHS + (4 links x 144 B + clover 576 B)/2
+      FP32: 192 B per RHS + (4 x (48 B rows + 8 B phase) + clover 288 B)/2
+      FP32 + BF16 links: 192 B per RHS + (4 x (24 B rows + 8 B phase) + 288 B)/2
+    """
+    per_rhs, shared = {0: (384.0, 576.0), 1: (192.0, 256.0), 2: (192.0, 208.0)}[prec]
+    return nsites2 * (per_rhs * rhs + shared * launches)
+
+
+def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
+    """The oracle's FP64 apply timed on the host cores (bounded sample)."""
+    import numpy as np
+
+    from oracle import dirac as odirac
+    from paper_2108_11989_amd import synth
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    t0 = time.time()
+    op = odirac.Operator(su3, th, q)
+    t_setup = time.time() - t0
+    psi = synth.random_spinor(T, L, 5)
+    n = 0
+    t0 = time.time()
+    while True:
+        psi = op.apply(psi, -0.3, True)
+        psi /= np.linalg.norm(psi)
+        n += 1
+        if time.time() - t0 > budget_s * 0.5 or n >= 20:
+            break
+    dt = time.time() - t0
+    return {"value": n / dt, "unit": "Dirac applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3 (clover setup {t_setup:.1f} s not counted)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched_32^4")
+    ap.add_argument("--k", type=int, default=3, help="eigenvalues (Kramers pairs) per mass point")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--path-points", type=int, default=0, help="use only the first n kappas (0 = all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(a single lattice or an ensemble would shard by configuration/flavour; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+
+    if not torch.cuda.is_available():
+        log("no GPU")
+        sys.exit(1)
+    w = synth.WORKLOADS[args.workload]
+    T, L, q = w["T"], w["L"], w["q"][0]
+    log(f"[bench] workload {args.workload}: {T}x{L}^3, eps {w['eps']}, seed {w['seed']}, smear {w['smear']}")
+    t0 = time.time()
+    su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
+    log(f"[bench] field generated in {time.time() - t0:.1f} s")
+    su3_d = torch.from_numpy(su3).cuda().contiguous()
+    th_d = torch.from_numpy(th).cuda().contiguous()
+    kappas = w["kappas"] if args.path_points <= 0 else w["kappas"][: args.path_points]
+    masses = np.asarray(synth.kappa_to_m0(kappas), dtype=np.float64)
+    inner = {"bf16": cstar.FP32_BF16LINKS, "fp32": cstar.FP32, "fp64": cstar.FP64}[args.inner]
+    opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000)
+    nsites2 = 2 * T * L ** 3
+
+    def step():
+        g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+        g.timing(True)
+        signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
+        tm = g.read_timing()
+        g.close()
+        return signs, rep, tm
+
+    for i in range(args.warmup):
+        t0 = time.time()
+        signs, rep, _ = step()
+        log(f"[bench] warmup {i}: {time.time() - t0:.2f} s, {rep.n_points} mass points, {rep.applies} applies")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    applies = 0
+    tms = []
+    for i in range(args.steps):
+        signs, rep, tm = step()
+        applies += rep.applies
+        tms.append(tm)
+        log(f"[bench] step {i}: {rep.n_points} points, {rep.applies} applies, crossings {rep.n_crossings}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"[bench] signs over the path: {''.join('+' if s > 0 else '-' for s in signs)}")
+
+    # dominant kernel: the precision with the most kernel time
+    ms = [sum(t[p]["ms"] for t in tms) for p in range(3)]
+    dom = int(np.argmax(ms))
+    launches = sum(t[dom]["launches"] for t in tms)
+    rhs = sum(t[dom]["rhs"] for t in tms)
+    byts = algorithmic_bytes(dom, nsites2, launches, rhs)
+    achieved = byts / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
+    kern_name = {0: "apply FP64", 1: "apply FP32", 2: "apply FP32/BF16-links"}[dom]
+    log(f"[bench] kernel time by precision (ms): {ms}; dominant {kern_name}: {launches} launches, "
+        f"{rhs} rhs, avg {ms[dom] / max(launches, 1):.3f} ms/launch, {achieved:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle")
+        cpu = cpu_baseline(su3, th, q, T, L)
+
+    out = {
+        "metric": "Dirac applies/s & HBM GB/s (% peak) at 32^4; s per Pfaffian sign, learned vs plain",
+        "value": applies / dt,
+        "unit": "Dirac applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "fp32+bf16-links/f64", "fp32": "f32/f64", "fp64": "f64"}[args.inner],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": f"{T}x{L}^3", "sites_doubled": nsites2,
+                   "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol,
+                   "inner": args.inner, "s_per_sign": dt / args.steps,
+                   "mass_points_solved": rep.n_points, "crossings": rep.n_crossings},
+        "roofline": {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": ms[dom] / max(launches, 1), "rhs_per_launch": rhs / max(launches, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

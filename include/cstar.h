@@ -1,0 +1,217 @@
+/*
+ * cstar.h -- C ABI of libcstar.so: the Wilson-clover Dirac operator with C*
+ * boundary conditions on MI355X (gfx950), its lowest eigenvalues and the sign
+ * of the Pfaffian (arXiv:2108.11989, section "Sign of the Pfaffian").
+ *
+ * General conventions
+ *  - Every entry point returns a cstar_status; no C++ exception crosses the ABI.
+ *    On failure cstar_last_error() returns a thread-local message.
+ *  - Host pointers are caller-owned and only read (or written, for outputs)
+ *    during the call.  Device pointers are caller-owned allocations on the
+ *    gauge handle's device; the library never frees them.
+ *  - All device work runs on the handle's stream (the stream passed at
+ *    creation; NULL = the default stream).  Calls returning host results are
+ *    synchronous; dirac_apply / pack / unpack are asynchronous.
+ *  - One handle must not be used from two threads at once.
+ *
+ * Lattice and fields (paper, simulation setup and sign-of-the-Pfaffian sections)
+ *  - Physical lattice T x L^3, T and L even and >= 2; coordinates (t,x1,x2,x3),
+ *    mu = 0 is t.  C* boundary conditions in space, periodic gauge field in
+ *    time, fermion time phase time_bc = +1 (periodic) or -1 (antiperiodic).
+ *  - C* is realised on the x-doubled lattice (x1 in [0,2L)): the sites with
+ *    x1 >= L hold the charge-conjugate field, so the operator acts on
+ *    2*T*L^3 sites x 12 complex components = the 24V x 24V matrix of the paper.
+ *  - su3: [T][L][L][L][4][3][3] complex128 (interleaved re,im), lexicographic
+ *    with t slowest and x3 fastest.  theta: [T][L][L][L][4] float64, the U(1)
+ *    angle; the quark link is exp(i q theta) U.  Only the physical lattice is
+ *    passed; the library builds the conjugate copy.
+ *  - Operator: (D psi)(x) = (4+m0) psi(x) + SW(x) psi(x)
+ *      - 1/2 sum_mu [(1-g_mu) V(x,mu) psi(x+mu) + (1+g_mu) V(x-mu,mu)^H psi(x-mu)],
+ *    SW = (i/4) sum_{mu,nu} sigma_{mu nu} [c_su3 Fhat_{mu nu} + q c_u1 Fhat^{U(1)}_{mu nu}],
+ *    Fhat = (Q - Q^H)/8 from the four clover leaves, chiral basis with
+ *    g5 = diag(1,1,-1,-1), C = i g0 g2.  Q = g5 D is Hermitian.
+ *
+ * Spinor layouts
+ *  - canonical: [nrhs][T][2L][L][L][4][3] complex (complex128 for CSTAR_FP64,
+ *    complex64 for the FP32 precisions).
+ *  - native (what dirac_apply and the solvers read): per right-hand side a
+ *    contiguous block of cstar_spinor_bytes() bytes, laid out as
+ *      FP64: double2 [parity 2][component 12][Vh][mirror 2]
+ *      FP32: float4  [parity 2][component-pair 6][Vh][mirror 2]
+ *    where Vh = T*L^3/2, parity = (t+x1+x2+x3) mod 2 of the physical site,
+ *    the in-parity index is (lexicographic physical index)/2, "mirror" is 0
+ *    for x1 < L and 1 for the conjugate copy at x1+L, and component =
+ *    3*spin + colour.  cstar_spinor_pack / _unpack convert between the two.
+ */
+#ifndef CSTAR_H
+#define CSTAR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cstar_gauge cstar_gauge;
+
+typedef enum {
+    CSTAR_OK = 0,
+    CSTAR_EINVAL = -1,  /* bad argument: sizes, NaN/Inf input, null pointer */
+    CSTAR_ENOMEM = -2,  /* device or host allocation failed */
+    CSTAR_EDEVICE = -3, /* HIP runtime error or no device */
+    CSTAR_ENOCONV = -4, /* eigensolver hit max_iter before tol */
+    CSTAR_EAMBIG = -5,  /* a sign could not be decided (eigenvalue at zero) */
+    CSTAR_ESTATE = -6   /* handle in a state that does not allow the call */
+} cstar_status;
+
+typedef enum {
+    CSTAR_FP64 = 0,           /* FP64 spinors, FP64 links (18 reals), FP64 clover */
+    CSTAR_FP32 = 1,           /* FP32 spinors, FP32 links (rows 0,1 + phase angle), FP32 clover */
+    CSTAR_FP32_BF16LINKS = 2  /* FP32 spinors, BF16 links (rows 0,1) + FP32 phase angle, FP32 clover */
+} cstar_prec;
+
+typedef struct {
+    int T, L;        /* physical lattice T x L^3 (even, >= 2) */
+    int time_bc;     /* +1 periodic, -1 antiperiodic fermion time boundary */
+    double q;        /* quark charge in units of the U(1) link angle */
+    double csw_su3;  /* SU(3) Sheikholeslami-Wohlert coefficient */
+    double csw_u1;   /* U(1) Sheikholeslami-Wohlert coefficient */
+} cstar_params;
+
+/* Thread-local message of the last failing call on this thread. */
+const char *cstar_last_error(void);
+
+/*
+ * Create a handle for one gauge field and one quark charge: copies su3/theta
+ * to the device, packs the links in every precision and computes the clover
+ * term in FP64 on the GPU.  src_on_device != 0: su3/theta are device pointers
+ * (same layout); the call then moves no data over PCIe.
+ * Errors: EINVAL for odd/small T, L, time_bc not +-1, non-finite parameters
+ * or field entries; ENOMEM; EDEVICE.
+ */
+cstar_status cstar_gauge_create(const cstar_params *params, const double *su3, const double *theta,
+                                int src_on_device, void *stream, cstar_gauge **out);
+void cstar_gauge_destroy(cstar_gauge *g);
+
+/* Bytes of one native spinor of precision prec (per right-hand side). */
+size_t cstar_spinor_bytes(const cstar_gauge *g, cstar_prec prec);
+/* Number of sites of the x-doubled lattice, 2*T*L^3. */
+long cstar_n_sites(const cstar_gauge *g);
+
+/* canonical <-> native conversion of nrhs spinors (device pointers, asynchronous). */
+cstar_status cstar_spinor_pack(cstar_gauge *g, cstar_prec prec, int nrhs, const void *canonical, void *native);
+cstar_status cstar_spinor_unpack(cstar_gauge *g, cstar_prec prec, int nrhs, const void *native, void *canonical);
+
+/*
+ * out_j = D(m_j) in_j   (gamma5 != 0: out_j = Q(m_j) in_j = g5 D(m_j) in_j),
+ * j < nrhs, on the x-doubled lattice (paper: D is the 24V x 24V operator on
+ * the quark/antiquark doublet).  in/out: native layout, device, nrhs blocks of
+ * cstar_spinor_bytes(prec) each, non-aliasing.  masses: host[nrhs] bare m0.
+ * nrhs == 1 runs the single-vector kernel; nrhs > 1 runs the multi-RHS
+ * kernel, which reads each link and clover entry once for all right-hand
+ * sides.  Asynchronous on the handle's stream.
+ */
+cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
+                         const void *in, void *out);
+
+typedef struct {
+    cstar_prec inner;        /* precision of the filter applies (FP64 or an FP32 form) */
+    double tol;              /* target: residual ||Q v - lambda v|| <= tol * max(|lambda|, lambda_floor) */
+    int max_iter;            /* outer iterations */
+    int block;               /* vectors per block (>= 2k; 0 = automatic) */
+    int degree;              /* Chebyshev filter degree (0 = automatic) */
+    int use_nn;              /* 1: learned preconditioner attached to the handle, if any */
+    int warm_start;          /* 1: start from the Ritz block of this handle's previous converged call */
+    unsigned long long seed; /* start vectors */
+} cstar_eig_opts;
+
+typedef struct {
+    int iterations;          /* outer iterations */
+    long applies_fp64;       /* single-RHS D applications in FP64 */
+    long applies_inner;      /* single-RHS D applications in the inner precision */
+    double seconds;          /* wall time of the call */
+    double lambda_max_est;   /* upper spectral bound used by the filter */
+} cstar_eig_stats;
+
+/*
+ * The k eigenvalues of Q(m0) = g5 D(m0) smallest in modulus, counted once
+ * per Kramers pair (paper: the spectrum of Q is doubly degenerate; lambda_n,
+ * n = 1..12V, lists each pair once), signed, sorted by |lambda| ascending
+ * (ties: lambda ascending).  evals/resid: host[k]; resid[i] is the FP64
+ * residual norm ||Q v_i - lambda_i v_i|| of a unit vector v_i, a rigorous
+ * bound on the distance of lambda_i to the spectrum.  evecs: nullable device
+ * pointer, k native FP64 spinors.  stats: nullable.  Synchronous.
+ * Errors: EINVAL (k < 1, k > 64), ENOCONV (max_iter reached; evals/resid hold
+ * the last iterate), ENOMEM, EDEVICE.
+ */
+cstar_status q_lowest_eigs(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts, double *evals,
+                           double *resid, void *evecs, cstar_eig_stats *stats);
+
+typedef struct {
+    cstar_eig_opts eig;  /* eigensolver options for every mass point */
+    int k;               /* eigenvalues per mass point (>= 1) */
+    double c;            /* step-A factor, slightly below 2 (paper); 0 = 1.9 */
+    double m_max;        /* mass above which no crossing is possible; <= 0: computed
+                            from the largest clover norm on the handle */
+} cstar_sign_opts;
+
+typedef struct {
+    int n_points;        /* mass points solved (path points + step-A / bisection points) */
+    double m[512];       /* the masses, in the order solved */
+    double lambda_bar[512];
+    int n_crossings;     /* certified zero crossings between the target and m_max */
+    long applies;        /* single-RHS D applications (all precisions) */
+    double seconds;
+} cstar_sign_report;
+
+/*
+ * Sign of the Pfaffian W_sgn(m_i) = sign pf[C T D(m_i)] at every mass of
+ * m_path (paper: pf[CTD] = prod_n lambda_n, so the sign flips each time an
+ * eigenvalue of Q crosses zero as m0 moves, and it is +1 at very large mass).
+ * The flow is followed upwards from min(m_path) to m_max with step A of the
+ * paper (m <- m + c*lambda_bar while lambda_bar grows, using the
+ * Feynman-Hellmann bound |lambda_n'(m0)| <= 1); a segment where the bound
+ * does not exclude a crossing is resolved by counting eigenvalues that pass
+ * zero between certified levels, splitting the segment if needed.
+ * m_path: host[n], any order.  sign_out: host[n], +1 or -1.  report: nullable.
+ * Errors: EINVAL; EAMBIG (an eigenvalue within its error bound of zero at a
+ * path point; sign_out holds 0 there); ENOCONV; ENOMEM; EDEVICE.
+ */
+cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cstar_sign_opts *opts,
+                           int *sign_out, cstar_sign_report *report);
+
+/*
+ * Host logic of pfaffian_sign over any eigenvalue provider (the same driver
+ * pfaffian_sign uses; a provider may be a test double).  provider(ctx, m, k,
+ * evals, errs) must fill the k eigenvalues of Q(m) smallest in modulus, one
+ * per Kramers pair, signed, with rigorous error bounds errs[], sorted by
+ * |lambda|, and return 0 (nonzero = failure, reported as ENOCONV).
+ */
+typedef int (*cstar_eig_provider)(void *ctx, double m, int k, double *evals, double *errs);
+cstar_status cstar_sign_driver(cstar_eig_provider provider, void *ctx, const double *m_path, int n,
+                               int k, double c, double m_max, int *sign_out, cstar_sign_report *report);
+
+/*
+ * Kernel timing of the Dirac-apply launches issued on this handle (by
+ * dirac_apply and by the solvers): when enabled, HIP events are recorded on
+ * the handle's stream around every launch.  Per precision p (cstar_prec):
+ * launches[p] kernel launches, rhs[p] right-hand sides they applied, ms[p]
+ * summed kernel time.  enable(on) resets the counters; read synchronises the
+ * stream.  Errors: EINVAL for a null handle; EDEVICE.
+ */
+typedef struct {
+    long launches[3];
+    long rhs[3];
+    double ms[3];
+} cstar_apply_timing;
+cstar_status cstar_timing_enable(cstar_gauge *g, int on);
+cstar_status cstar_timing_read(cstar_gauge *g, cstar_apply_timing *out);
+
+/* Largest spectral norm over sites of the clover term SW(x) (bounds the
+ * mass above which Q(m) has no eigenvalue near zero: sigma_min(D) >= m0 - this). */
+cstar_status cstar_clover_norm_max(cstar_gauge *g, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

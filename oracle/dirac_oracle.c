@@ -244,8 +244,9 @@ static double to_bf16(double v) {
  * link_mode 0: V = exp(i q theta_e) U_e in FP64.
  * link_mode 1/2: the compressed formats -- rows 0 and 1 of the physical SU(3)
  *   link rounded to FP32 (1) or BF16 (2), row 2 = conj(row0 x row1), the
- *   quark phase angle phi = q*theta rounded to FP32; the mirror copy is the
- *   complex conjugate of the physical one.  Arithmetic stays FP64.
+ *   quark phase exp(i q theta) stored as its cosine and sine each rounded to
+ *   FP32; the mirror copy is the complex conjugate of the physical one.
+ *   Arithmetic stays FP64.
  */
 static void build_links(const geom *g, const double *su3, const double *theta, double q,
                         int link_mode, cplx *Vtab) {
@@ -278,8 +279,8 @@ static void build_links(const geom *g, const double *su3, const double *theta, d
                 R[2][0] = conj(R[0][1] * R[1][2] - R[0][2] * R[1][1]);
                 R[2][1] = conj(R[0][2] * R[1][0] - R[0][0] * R[1][2]);
                 R[2][2] = conj(R[0][0] * R[1][1] - R[0][1] * R[1][0]);
-                double phi = (double)(float)(q * th);
-                cplx ph = cexp(I * phi);
+                double phi = q * th;
+                cplx ph = (double)(float)cos(phi) + I * (double)(float)sin(phi);
                 for (int i = 0; i < 3; i++)
                     for (int j = 0; j < 3; j++) {
                         cplx v = ph * R[i][j];

@@ -1,0 +1,527 @@
+// Lowest |eigenvalues| of Q(m) = g5 D(m) on the GPU: block Chebyshev-Davidson
+// iteration on A = Q^2 (Zhou & Saad, "A Chebyshev-Davidson algorithm for large
+// symmetric eigenproblems", SIAM J. Matrix Anal. Appl. 29 (2007)) with
+// Rayleigh-Ritz in FP64, followed by Rayleigh-Ritz with Q itself in the
+// converged subspace to give signed eigenvalues and rigorous residual bounds.
+//
+// The spectrum of Q is doubly degenerate (paper: v and C T g5 v^* are
+// orthogonal eigenvectors with the same eigenvalue), so k eigenvalues counted
+// once per pair need a block of at least 2k vectors.  Each iteration:
+//   Y = p_d(A) X        Chebyshev filter of degree d damping [a_cut, b_up]
+//                       (inner precision: FP32 with FP32 or BF16 links, or FP64)
+//   Y <- orth(Y - X X^H Y)                       FP64, SVQB orthonormalisation
+//   [X Y] Rayleigh-Ritz with A in FP64 (A applied in FP64) -> keep nb lowest
+//   Rayleigh-Ritz of Q on X -> signed lambda, residuals ||Q z - lambda z||
+// Mixed precision: the filter runs in the inner precision until the wanted
+// residuals reach its noise floor, then in FP64 (refinement).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "blas.h"
+#include "cstar_internal.h"
+#include "dense_eig.h"
+#include "eig.h"
+
+namespace cstar {
+
+struct Workspace {
+    int nb = 0;
+    long n = 0;                 // complex entries per FP64 vector
+    double2 *XY = nullptr;      // 2nb vectors: X = [0,nb), Y = [nb,2nb)
+    double2 *AXY = nullptr;     // 2nb vectors: A X, A Y
+    double2 *T = nullptr;       // nb vectors
+    double2 *T2 = nullptr;      // nb vectors
+    float4 *F[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32 filter blocks (nb each)
+    double2 *partial = nullptr;
+    double2 *G = nullptr;       // device small matrix (up to 128 x 128)
+    double2 *C = nullptr;
+    int warm_nb = 0;            // > 0: X holds the Ritz block of the last converged call
+    std::vector<void *> owned;
+};
+
+static void ws_free(Workspace *w) {
+    if (!w) return;
+    for (void *p : w->owned) (void)hipFree(p);
+    delete w;
+}
+
+void workspace_release(cstar_gauge *g) {
+    ws_free(g->ws);
+    g->ws = nullptr;
+}
+
+static cstar_status ws_get(cstar_gauge *g, int nb, Workspace **out) {
+    const long n = n_cplx(g->geo);
+    if (g->ws && g->ws->nb >= nb && g->ws->n == n) {
+        *out = g->ws;
+        return CSTAR_OK;
+    }
+    workspace_release(g);
+    Workspace *w = new Workspace();
+    w->nb = nb;
+    w->n = n;
+    auto alloc = [&](size_t bytes, void **p) -> bool {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        w->owned.push_back(*p);
+        return true;
+    };
+    const size_t v64 = (size_t)n * sizeof(double2), v32 = (size_t)n / 2 * sizeof(float4);
+    bool ok = alloc(2 * nb * v64, (void **)&w->XY) && alloc(2 * nb * v64, (void **)&w->AXY) &&
+              alloc(nb * v64, (void **)&w->T) && alloc(nb * v64, (void **)&w->T2) &&
+              alloc(gram_partial_bytes(), (void **)&w->partial) && alloc(128 * 128 * sizeof(double2), (void **)&w->G) &&
+              alloc(128 * 128 * sizeof(double2), (void **)&w->C);
+    for (int i = 0; i < 4 && ok; i++) ok = alloc(nb * v32, (void **)&w->F[i]);
+    if (!ok) {
+        (void)hipGetLastError();
+        ws_free(w);
+        return fail(CSTAR_ENOMEM, "eigensolver workspace allocation failed");
+    }
+    g->ws = w;
+    *out = w;
+    return CSTAR_OK;
+}
+
+namespace {
+
+struct Ctx {
+    cstar_gauge *g;
+    Workspace *w;
+    hipStream_t s;
+    double m;
+    long ap64 = 0, ap_inner = 0;
+};
+
+// out = Q in on nv FP64 vectors
+hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv) {
+    ApplyArgs a{in, out, (long)c.w->n * (long)sizeof(double2), nv, 1, nullptr, c.m};
+    c.ap64 += nv;
+    return handle_apply(c.g, CSTAR_FP64, a);
+}
+hipError_t q32(Ctx &c, cstar_prec prec, const float4 *in, float4 *out, int nv) {
+    ApplyArgs a{in, out, (long)c.w->n / 2 * (long)sizeof(float4), nv, 1, nullptr, c.m};
+    c.ap_inner += nv;
+    return handle_apply(c.g, prec, a);
+}
+
+// host copy of a device gram matrix V^H W (nv x nw), tiled in 64 x 64 pieces
+cstar_status gram(Ctx &c, const double2 *V, int nv, const double2 *W, int nw, std::vector<zd> &G) {
+    G.assign((size_t)nv * nw, zd(0, 0));
+    const long n = c.w->n;
+    std::vector<double2> tile(64 * 64);
+    for (int i0 = 0; i0 < nv; i0 += 64)
+        for (int j0 = 0; j0 < nw; j0 += 64) {
+            const int bi = std::min(64, nv - i0), bj = std::min(64, nw - j0);
+            CSTAR_HIP(launch_gram(V + (long)i0 * n, n, bi, W + (long)j0 * n, n, bj, n, c.w->partial, c.w->G, c.s));
+            CSTAR_HIP(hipMemcpyAsync(tile.data(), c.w->G, sizeof(double2) * bi * bj, hipMemcpyDeviceToHost, c.s));
+            CSTAR_HIP(hipStreamSynchronize(c.s));
+            for (int i = 0; i < bi; i++)
+                for (int j = 0; j < bj; j++)
+                    G[(size_t)(i0 + i) * nw + j0 + j] = zd(tile[i * bj + j].x, tile[i * bj + j].y);
+        }
+    return CSTAR_OK;
+}
+
+// O = V C with C (nv x no) host row-major
+cstar_status combine(Ctx &c, const double2 *V, int nv, const std::vector<zd> &C, int no, double2 *O) {
+    std::vector<double2> h((size_t)nv * no);
+    for (size_t i = 0; i < h.size(); i++) h[i] = make_double2(C[i].real(), C[i].imag());
+    CSTAR_HIP(hipMemcpyAsync(c.w->C, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, c.s));
+    CSTAR_HIP(launch_combine(V, c.w->n, nv, c.w->C, no, O, c.w->n, no, c.w->n, c.s));
+    CSTAR_HIP(hipStreamSynchronize(c.s));  // C staging buffer is reused by the next call
+    return CSTAR_OK;
+}
+
+// Orthonormalise the nv vectors at Y in place against themselves (SVQB:
+// G = Y^H Y = U S U^H, Y <- Y U S^{-1/2}, dropping directions below drop_tol).
+// Returns the number of vectors kept (compacted to the front of Y).
+cstar_status orthonormalise(Ctx &c, double2 *Y, int nv, double2 *tmp, int *kept) {
+    std::vector<zd> G;
+    cstar_status st = gram(c, Y, nv, Y, nv, G);
+    if (st) return st;
+    std::vector<double> d(nv);
+    for (int i = 0; i < nv; i++) d[i] = std::sqrt(std::max(G[(size_t)i * nv + i].real(), 1e-300));
+    std::vector<zd> Gs((size_t)nv * nv);
+    for (int i = 0; i < nv; i++)
+        for (int j = 0; j < nv; j++) Gs[(size_t)i * nv + j] = G[(size_t)i * nv + j] / (d[i] * d[j]);
+    std::vector<double> w;
+    std::vector<zd> U;
+    herm_eig(nv, Gs, w, U);
+    const double wmax = w.empty() ? 0.0 : w.back();
+    std::vector<int> keep;
+    for (int j = nv - 1; j >= 0; j--)
+        if (w[j] > 1e-13 * wmax) keep.push_back(j);
+    const int nk = (int)keep.size();
+    std::vector<zd> Cm((size_t)nv * nk);
+    for (int i = 0; i < nv; i++)
+        for (int jj = 0; jj < nk; jj++) Cm[(size_t)i * nk + jj] = U[(size_t)i * nv + keep[jj]] / (d[i] * std::sqrt(w[keep[jj]]));
+    st = combine(c, Y, nv, Cm, nk, tmp);
+    if (st) return st;
+    CSTAR_HIP(hipMemcpyAsync(Y, tmp, sizeof(double2) * c.w->n * nk, hipMemcpyDeviceToDevice, c.s));
+    *kept = nk;
+    return CSTAR_OK;
+}
+
+// Y <- Y - X (X^H Y)
+cstar_status project_out(Ctx &c, const double2 *X, int nx, double2 *Y, int ny, double2 *tmp) {
+    std::vector<zd> G;
+    cstar_status st = gram(c, X, nx, Y, ny, G);
+    if (st) return st;
+    st = combine(c, X, nx, G, ny, tmp);
+    if (st) return st;
+    CSTAR_HIP(launch_lincomb64(2L * c.w->n * ny, -1.0, (const double *)tmp, 1.0, (double *)Y, 0.0, nullptr, c.s));
+    return CSTAR_OK;
+}
+
+// Rayleigh-Ritz of H = V^H A V in the basis V (nt vectors) with its overlap
+// M = V^H V (the basis is orthonormal only up to rounding): with
+// M = U S U^H and B = U S^{-1/2} over the well-conditioned directions, the
+// Ritz pairs are eig(B^H H B) = (theta, Z) and the Ritz vectors V B Z.
+// Returns theta ascending and the coefficient matrix C = B Z (nt x r).
+void rr_generalised(int nt, const std::vector<zd> &H, const std::vector<zd> &M, std::vector<double> &theta,
+                    std::vector<zd> &C, int *rank) {
+    std::vector<double> sg;
+    std::vector<zd> U;
+    herm_eig(nt, M, sg, U);
+    const double smax = sg.empty() ? 0.0 : sg.back();
+    std::vector<int> keep;
+    for (int j = nt - 1; j >= 0; j--)
+        if (sg[j] > 1e-12 * smax) keep.push_back(j);
+    const int r = (int)keep.size();
+    std::vector<zd> B((size_t)nt * r);
+    for (int i = 0; i < nt; i++)
+        for (int jj = 0; jj < r; jj++) B[(size_t)i * r + jj] = U[(size_t)i * nt + keep[jj]] / std::sqrt(sg[keep[jj]]);
+    // Hr = B^H H B
+    std::vector<zd> HB((size_t)nt * r, zd(0, 0)), Hr((size_t)r * r, zd(0, 0));
+    for (int i = 0; i < nt; i++)
+        for (int l = 0; l < nt; l++) {
+            const zd h = H[(size_t)i * nt + l];
+            if (h == zd(0, 0)) continue;
+            for (int jj = 0; jj < r; jj++) HB[(size_t)i * r + jj] += h * B[(size_t)l * r + jj];
+        }
+    for (int a = 0; a < r; a++)
+        for (int i = 0; i < nt; i++) {
+            const zd b = std::conj(B[(size_t)i * r + a]);
+            for (int jj = 0; jj < r; jj++) Hr[(size_t)a * r + jj] += b * HB[(size_t)i * r + jj];
+        }
+    std::vector<zd> Z;
+    herm_eig(r, Hr, theta, Z);
+    C.assign((size_t)nt * r, zd(0, 0));
+    for (int i = 0; i < nt; i++)
+        for (int l = 0; l < r; l++) {
+            const zd b = B[(size_t)i * r + l];
+            for (int jj = 0; jj < r; jj++) C[(size_t)i * r + jj] += b * Z[(size_t)l * r + jj];
+        }
+    *rank = r;
+}
+
+// Chebyshev filter Y = T_d(x(A)) X / T_d(x(a0)), x(t) = (t - cen)/e, in FP64.
+// Three-term recurrence with the normalisation sigma_j = T_{j-1}(x0)/T_j(x0):
+//   Y_1 = sigma_1/e (A - cen) X,  Y_{j+1} = 2 sigma_{j+1}/e (A - cen) Y_j - sigma_j sigma_{j+1} Y_{j-1},
+//   sigma_1 = 1/x0, sigma_{j+1} = 1/(2 x0 - sigma_j).
+// Buffers: three rotating blocks (Yout, B1, B2) and one for Q * Y_j (BQ); X is read only.
+cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0, double acut, double bup, int deg,
+                      double2 *B1, double2 *B2, double2 *BQ) {
+    const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
+    const double x0 = (a0 - cen) / e;
+    double sig = 1.0 / x0;
+    const long nr = 2L * c.w->n * nv;
+    double2 *buf[3] = {Yout, B1, B2};
+    int icur = 0, iprev = -1;  // iprev = -1 means X
+    CSTAR_HIP(q64(c, X, BQ, nv));
+    CSTAR_HIP(q64(c, BQ, buf[icur], nv));
+    CSTAR_HIP(launch_lincomb64(nr, -cen * sig / e, (const double *)X, sig / e, (double *)buf[icur], 0.0, nullptr,
+                               c.s));
+    for (int j = 1; j < deg; j++) {
+        const double sig2 = 1.0 / (2.0 * x0 - sig);
+        int inext = 0;
+        while (inext == icur || inext == iprev) inext++;
+        const double2 *prev = iprev < 0 ? X : buf[iprev];
+        CSTAR_HIP(q64(c, buf[icur], BQ, nv));
+        CSTAR_HIP(q64(c, BQ, buf[inext], nv));
+        CSTAR_HIP(launch_lincomb64(nr, -2.0 * sig2 * cen / e, (const double *)buf[icur], 2.0 * sig2 / e,
+                                   (double *)buf[inext], -sig * sig2, (const double *)prev, c.s));
+        iprev = icur;
+        icur = inext;
+        sig = sig2;
+    }
+    if (icur != 0)
+        CSTAR_HIP(hipMemcpyAsync(Yout, buf[icur], sizeof(double2) * c.w->n * nv, hipMemcpyDeviceToDevice, c.s));
+    return CSTAR_OK;
+}
+
+// The same filter in FP32 on the F[] buffers: F[0] = X (converted), result converted to Yout.
+cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2 *Yout, double a0, double acut,
+                      double bup, int deg) {
+    Workspace *w = c.w;
+    const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
+    const double x0 = (a0 - cen) / e;
+    double sig = 1.0 / x0;
+    const long nr = 2L * w->n * nv;  // reals
+    float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
+    CSTAR_HIP(launch_to_f32(c.g->geo, nv, X, prev, c.s));
+    CSTAR_HIP(q32(c, prec, prev, tq, nv));
+    CSTAR_HIP(q32(c, prec, tq, cur, nv));
+    CSTAR_HIP(launch_lincomb32(nr, (float)(-cen * sig / e), (const float *)prev, (float)(sig / e), (float *)cur, 0.f,
+                               nullptr, c.s));
+    for (int j = 1; j < deg; j++) {
+        const double sig2 = 1.0 / (2.0 * x0 - sig);
+        CSTAR_HIP(q32(c, prec, cur, tq, nv));
+        CSTAR_HIP(q32(c, prec, tq, nxt, nv));
+        CSTAR_HIP(launch_lincomb32(nr, (float)(-2.0 * sig2 * cen / e), (const float *)cur, (float)(2.0 * sig2 / e),
+                                   (float *)nxt, (float)(-sig * sig2), (const float *)prev, c.s));
+        float4 *t = prev;
+        prev = cur;
+        cur = nxt;
+        nxt = t;
+        sig = sig2;
+    }
+    CSTAR_HIP(launch_to_f64(c.g->geo, nv, cur, Yout, c.s));
+    return CSTAR_OK;
+}
+
+}  // namespace
+
+cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts_in, double *evals, double *resid,
+                        void *evecs, cstar_eig_stats *stats, const EigHooks *hooks) {
+    const auto t_start = std::chrono::steady_clock::now();
+    cstar_eig_opts o{};
+    o.inner = CSTAR_FP32_BF16LINKS;
+    o.tol = 1e-10;
+    o.max_iter = 200;
+    if (opts_in) o = *opts_in;
+    if (k < 1 || k > 30) return fail(CSTAR_EINVAL, "q_lowest_eigs: k must be in [1, 30]");
+    if (!(o.tol > 0) || o.max_iter < 1) return fail(CSTAR_EINVAL, "q_lowest_eigs: bad tol/max_iter");
+    int nb = o.block > 0 ? o.block : 2 * k + std::max(4, k / 2);
+    nb = std::max(nb, 2 * k);
+    if (nb > 64) return fail(CSTAR_EINVAL, "q_lowest_eigs: block must be <= 64");
+    int deg = o.degree > 0 ? o.degree : 24;
+    const int deg_max = std::max(deg, 800);
+    Workspace *w = nullptr;
+    cstar_status st = ws_get(g, nb, &w);
+    if (st) return st;
+    Ctx c{g, w, g->stream, m0};
+    const long n = w->n;
+    double2 *X = w->XY, *Y = w->XY + (long)nb * n;
+    double2 *AX = w->AXY, *AY = w->AXY + (long)nb * n;
+
+    // rigorous upper bound of A = Q^2: ||D|| <= |4+m| + 4 + max_x ||SW(x)||
+    const double qb = std::fabs(4.0 + m0) + 4.0 + std::max(0.0, g->clover_norm_max);
+    const double bup = qb * qb * 1.0001;
+
+    // start block: the previous call's Ritz block on this handle (the flow is
+    // followed in small mass steps, so the low modes change little), else Gaussian
+    const bool warm = o.warm_start && w->warm_nb == nb;
+    if (!warm) CSTAR_HIP(launch_gauss(X, n * nb, o.seed ? o.seed : 0x5eedull, c.s));
+    w->warm_nb = 0;
+    int kept = 0;
+    st = orthonormalise(c, X, nb, w->T, &kept);
+    if (st) return st;
+    if (kept < nb) return fail(CSTAR_EDEVICE, "start block lost rank");
+    CSTAR_HIP(q64(c, X, w->T, nb));
+    CSTAR_HIP(q64(c, w->T, AX, nb));
+
+    std::vector<double> theta(nb, 0.0);
+    double acut = bup * 0.25, a0 = 0.0;
+    bool have_ritz = false;
+    cstar_prec inner = o.inner;
+    const char *venv = getenv("CSTAR_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
+    bool fp64_filter = (inner == CSTAR_FP64);
+    double last_rmax = 1e300, last_rabs = 1e300;
+    int stall = 0;
+    std::vector<double> lam_out(k), res_out(k);
+    bool converged = false;
+    int it = 0;
+    // signed Ritz data of the last iteration
+    for (it = 0; it < o.max_iter; it++) {
+        int ny = nb;
+        if (have_ritz) {
+            // ---- filter
+            if (hooks && hooks->precondition && o.use_nn) {
+                st = hooks->precondition(hooks->ctx, g, m0, X, nb, Y);
+                if (st) return st;
+            } else if (fp64_filter) {
+                st = filter64(c, X, nb, Y, a0, acut, bup, deg, w->T, w->T2, AY);
+            } else {
+                st = filter32(c, inner, X, nb, Y, a0, acut, bup, deg);
+            }
+            if (st) return st;
+            // ---- orthogonalise against X twice, then within
+            for (int r = 0; r < 2; r++) {
+                st = project_out(c, X, nb, Y, nb, w->T);
+                if (st) return st;
+            }
+            st = orthonormalise(c, Y, nb, w->T, &ny);
+            if (st) return st;
+            if (ny > 0) {
+                st = project_out(c, X, nb, Y, ny, w->T);
+                if (st) return st;
+                st = orthonormalise(c, Y, ny, w->T, &ny);
+                if (st) return st;
+            }
+            if (ny > 0) {
+                CSTAR_HIP(q64(c, Y, w->T, ny));
+                CSTAR_HIP(q64(c, w->T, AY, ny));
+            }
+        } else {
+            ny = 0;
+        }
+        // ---- Rayleigh-Ritz with A on [X Y] (generalised: overlap computed, not assumed)
+        const int nt = nb + ny;
+        std::vector<zd> H, Mo;
+        st = gram(c, w->XY, nt, w->AXY, nt, H);
+        if (st) return st;
+        st = gram(c, w->XY, nt, w->XY, nt, Mo);
+        if (st) return st;
+        std::vector<double> th;
+        std::vector<zd> S;
+        int rank = 0;
+        rr_generalised(nt, H, Mo, th, S, &rank);
+        if (rank < nb) return fail(CSTAR_EDEVICE, "q_lowest_eigs: search basis lost rank");
+        std::vector<zd> Sk((size_t)nt * nb);
+        for (int i = 0; i < nt; i++)
+            for (int j = 0; j < nb; j++) Sk[(size_t)i * nb + j] = S[(size_t)i * rank + j];
+        st = combine(c, w->XY, nt, Sk, nb, w->T);
+        if (st) return st;
+        st = combine(c, w->AXY, nt, Sk, nb, w->T2);
+        if (st) return st;
+        CSTAR_HIP(hipMemcpyAsync(X, w->T, sizeof(double2) * n * nb, hipMemcpyDeviceToDevice, c.s));
+        CSTAR_HIP(hipMemcpyAsync(AX, w->T2, sizeof(double2) * n * nb, hipMemcpyDeviceToDevice, c.s));
+        for (int j = 0; j < nb; j++) theta[j] = th[j];
+        a0 = std::max(0.0, std::min(theta[0], theta[0] - 0.01 * (theta[nb - 1] - theta[0])));
+        acut = theta[nb - 1];
+        if (acut >= bup) acut = 0.5 * bup;
+        have_ritz = true;
+
+        // ---- signed Rayleigh-Ritz with Q on X: QX in the Y slot
+        CSTAR_HIP(q64(c, X, Y, nb));
+        std::vector<zd> HQ, MX;
+        st = gram(c, X, nb, Y, nb, HQ);
+        if (st) return st;
+        st = gram(c, X, nb, X, nb, MX);
+        if (st) return st;
+        std::vector<double> lq;
+        std::vector<zd> SQfull;
+        int rq = 0;
+        rr_generalised(nb, HQ, MX, lq, SQfull, &rq);
+        if (rq < nb) return fail(CSTAR_EDEVICE, "q_lowest_eigs: Ritz block lost rank");
+        std::vector<zd> &SQ = SQfull;
+        // R = Q X S - X S diag(lq) = [X, QX] [-S L; S]
+        std::vector<zd> RC((size_t)2 * nb * nb);
+        for (int i = 0; i < nb; i++)
+            for (int j = 0; j < nb; j++) {
+                RC[(size_t)i * nb + j] = -SQ[(size_t)i * nb + j] * lq[j];
+                RC[(size_t)(nb + i) * nb + j] = SQ[(size_t)i * nb + j];
+            }
+        st = combine(c, w->XY, 2 * nb, RC, nb, w->T);
+        if (st) return st;
+        std::vector<zd> RR;
+        st = gram(c, w->T, nb, w->T, nb, RR);
+        if (st) return st;
+        std::vector<double> rn(nb);
+        for (int j = 0; j < nb; j++) rn[j] = std::sqrt(std::max(0.0, RR[(size_t)j * nb + j].real()));
+        // Kramers pairing: walk the signed Ritz values upwards and pair neighbours
+        // that agree within their residuals; then order pairs by |lambda|.
+        std::vector<int> ord(nb);
+        for (int j = 0; j < nb; j++) ord[j] = j;
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return lq[a] < lq[b]; });
+        struct Pr { double lam, err; int a; };
+        std::vector<Pr> prs;
+        const double qscale = std::sqrt(bup);
+        for (int i = 0; i + 1 < nb;) {
+            const int a = ord[i], b = ord[i + 1];
+            const double gap = std::fabs(lq[a] - lq[b]);
+            if (gap <= 2.0 * (rn[a] + rn[b]) + 1e-13 * qscale) {
+                prs.push_back({0.5 * (lq[a] + lq[b]), std::max(rn[a], rn[b]) + 0.5 * gap, a});
+                i += 2;
+            } else {
+                i += 1;
+            }
+        }
+        std::sort(prs.begin(), prs.end(), [](const Pr &x, const Pr &y) {
+            const double fa = std::fabs(x.lam), fb = std::fabs(y.lam);
+            return fa != fb ? fa < fb : x.lam < y.lam;
+        });
+        bool ok = (int)prs.size() >= k;
+        double rmax = ok ? 0.0 : 1e300;
+        // converged: residual below tol relative to |lambda| (floored at 1e-3), or
+        // at the FP64 rounding level of the residual itself (~ eps * ||Q|| * sqrt(dim))
+        const double noise = 256.0 * 2.2e-16 * qscale;
+        for (int i = 0; i < k && i < (int)prs.size(); i++) {
+            lam_out[i] = prs[i].lam;
+            res_out[i] = prs[i].err;
+            const double target = std::max(o.tol * std::max(std::fabs(lam_out[i]), 1e-3), noise);
+            if (res_out[i] > target) ok = false;
+            rmax = std::max(rmax, res_out[i] / std::max(std::fabs(lam_out[i]), 1e-3));
+        }
+        if (verbose)
+            fprintf(stderr, "[cstar eig] m=%.6f it=%d nb=%d ny=%d deg=%d pairs=%zu fp64filter=%d acut=%.3e rmax=%.3e lam0=%.6e res0=%.2e\n",
+                    m0, it, nb, ny, deg, prs.size(), (int)fp64_filter, acut, rmax, prs.empty() ? 0.0 : prs[0].lam,
+                    prs.empty() ? 0.0 : prs[0].err);
+        // a wanted pair must also be separated from the unpaired / guard Ritz values
+        if (ok) {
+            converged = true;
+            if (evecs) {
+                std::vector<zd> Sv((size_t)nb * k);
+                for (int i = 0; i < nb; i++)
+                    for (int j = 0; j < k; j++) Sv[(size_t)i * k + j] = SQ[(size_t)i * nb + prs[j].a];
+                st = combine(c, X, nb, Sv, k, (double2 *)evecs);
+                if (st) return st;
+            }
+            w->warm_nb = nb;
+            it++;
+            break;
+        }
+        // precision switch: the inner filter generates search directions until the
+        // wanted residuals reach its noise floor (the inner operator differs from
+        // the FP64 one by ~2^-8 relative for BF16 links, ~2^-23 for FP32), or stop
+        // improving for three iterations; then the filter runs in FP64.
+        double rabs = 0.0;
+        for (int i = 0; i < k && i < (int)prs.size(); i++) rabs = std::max(rabs, prs[i].err);
+        if ((int)prs.size() < k) rabs = 1e300;
+        const double floor_inner = (inner == CSTAR_FP32_BF16LINKS ? 4e-3 : 1e-6) * qscale;
+        stall = (rabs > 0.8 * last_rabs) ? stall + 1 : 0;
+        if (!fp64_filter && (rabs < 20.0 * floor_inner || stall >= 3)) {
+            fp64_filter = true;
+            stall = 0;
+        }
+        // filter degree: about two e-folds of damping per iteration between the
+        // wanted Ritz values and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up)
+        if (o.degree <= 0 && (int)theta.size() >= 2 * k) {
+            const double gap = acut - theta[2 * k - 1];
+            if (gap > 0) {
+                const double want = std::ceil(2.0 / (2.0 * std::sqrt(gap / bup)));
+                deg = (int)std::min<double>(deg_max, std::max<double>(16.0, want));
+            } else if (stall) {
+                deg = std::min(deg_max, deg + deg / 2);
+            }
+        } else if (stall && deg < deg_max) {
+            deg = std::min(deg_max, deg + deg / 2);
+        }
+        last_rmax = rmax;
+        last_rabs = rabs;
+    }
+    CSTAR_HIP(hipStreamSynchronize(c.s));
+    for (int i = 0; i < k; i++) {
+        evals[i] = lam_out[i];
+        if (resid) resid[i] = res_out[i];
+    }
+    if (stats) {
+        stats->iterations = it;
+        stats->applies_fp64 = c.ap64;
+        stats->applies_inner = c.ap_inner;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        stats->lambda_max_est = bup;
+    }
+    if (!converged) return fail(CSTAR_ENOCONV, "q_lowest_eigs: max_iter reached");
+    return CSTAR_OK;
+}
+
+}  // namespace cstar

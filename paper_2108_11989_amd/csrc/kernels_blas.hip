@@ -1,0 +1,232 @@
+// Vector kernels of the eigensolver on native spinor blocks (gfx950).
+//
+// An FP64 block holds nv vectors of n complex entries (double2), vector i at
+// base + i*ld.  FP32 native vectors (float4 = two complex entries) are only
+// touched by the elementwise kernels and the precision conversions.
+//
+//  * gram: G[i][j] = sum_n conj(V_i[n]) W_j[n] (FP64), LDS-staged tiles of
+//    both blocks, one partial matrix per workgroup, then a fixed-order sum
+//    over workgroups (bit-reproducible);
+//  * combine: Out_j = sum_i V_i C[i][j] (block rotation / projection);
+//  * lincomb: y = a x + b y + c z elementwise (real a,b,c), FP64 or FP32;
+//  * precision conversion between the FP64 and FP32 native layouts;
+//  * Gaussian fill from a counter-based hash.
+#include "cstar_internal.h"
+#include "blas.h"
+
+namespace cstar {
+
+constexpr int GT = 64;   // max vectors per side of one gram tile
+constexpr int GNC = 16;  // entries of n per LDS stage
+
+__global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, long ldv, int nv,
+                                              const double2 *__restrict__ W, long ldw, int nw, long n,
+                                              double2 *__restrict__ partial) {
+    __shared__ double2 sV[GT][GNC + 1];
+    __shared__ double2 sW[GT][GNC + 1];
+    const int tid = threadIdx.x;
+    const int ti = tid & 15, tj = tid >> 4;
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = make_double2(0.0, 0.0);
+    const long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long n0 = (long)blockIdx.x * chunk;
+    const long n1 = n0 + chunk < n ? n0 + chunk : n;
+    for (long base = n0; base < n1; base += GNC) {
+        // stage GNC entries of every vector
+        for (int e = tid; e < (nv + nw) * GNC; e += 256) {
+            const int vec = e / GNC, off = e % GNC;
+            const long idx = base + off;
+            double2 val = make_double2(0.0, 0.0);
+            if (vec < nv) {
+                if (idx < n1) val = V[(long)vec * ldv + idx];
+                sV[vec][off] = val;
+            } else {
+                if (idx < n1) val = W[(long)(vec - nv) * ldw + idx];
+                sW[vec - nv][off] = val;
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < GNC; k++) {
+            double2 v[4], w[4];
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                const int i = ti + 16 * a, j = tj + 16 * a;
+                v[a] = i < nv ? sV[i][k] : make_double2(0.0, 0.0);
+                w[a] = j < nw ? sW[j][k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    acc[a][b].x += v[a].x * w[b].x + v[a].y * w[b].y;
+                    acc[a][b].y += v[a].x * w[b].y - v[a].y * w[b].x;
+                }
+        }
+        __syncthreads();
+    }
+    double2 *P = partial + (long)blockIdx.x * GT * GT;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int i = ti + 16 * a, j = tj + 16 * b;
+            if (i < nv && j < nw) P[i * GT + j] = acc[a][b];
+        }
+}
+
+__global__ void k_gram_reduce(const double2 *__restrict__ partial, int nblk, int nv, int nw,
+                              double2 *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nv * nw) return;
+    const int i = e / nw, j = e % nw;
+    double sx = 0.0, sy = 0.0;
+    for (int b = 0; b < nblk; b++) {
+        const double2 v = partial[(long)b * GT * GT + i * GT + j];
+        sx += v.x;
+        sy += v.y;
+    }
+    out[e] = make_double2(sx, sy);
+}
+
+int gram_blocks() { return 1024; }
+size_t gram_partial_bytes() { return (size_t)gram_blocks() * GT * GT * sizeof(double2); }
+
+hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, long ldw, int nw, long n,
+                       double2 *partial, double2 *out_dev, hipStream_t s) {
+    if (nv > GT || nw > GT) return hipErrorInvalidValue;
+    const int nblk = gram_blocks();
+    hipLaunchKernelGGL(k_gram, dim3(nblk), dim3(256), 0, s, V, ldv, nv, W, ldw, nw, n, partial);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((nv * nw + 255) / 256), dim3(256), 0, s, partial, nblk, nv, nw, out_dev);
+    return hipGetLastError();
+}
+
+// Out_j[n] = sum_i V_i[n] C[i*ldc + j]  (i < nv, j < no), C complex in device memory
+constexpr int CJ = 8;
+__global__ __launch_bounds__(256) void k_combine(const double2 *__restrict__ V, long ldv, int nv,
+                                                 const double2 *__restrict__ C, int ldc, double2 *__restrict__ O,
+                                                 long ldo, int no, long n) {
+    __shared__ double2 sC[128 * CJ];
+    const int j0 = blockIdx.y * CJ;
+    for (int e = threadIdx.x; e < nv * CJ; e += blockDim.x) {
+        const int i = e / CJ, jj = e % CJ;
+        sC[e] = (j0 + jj < no) ? C[i * ldc + j0 + jj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+        double2 acc[CJ];
+#pragma unroll
+        for (int jj = 0; jj < CJ; jj++) acc[jj] = make_double2(0.0, 0.0);
+        for (int i = 0; i < nv; i++) {
+            const double2 v = V[(long)i * ldv + idx];
+#pragma unroll
+            for (int jj = 0; jj < CJ; jj++) {
+                const double2 c = sC[i * CJ + jj];
+                acc[jj].x += v.x * c.x - v.y * c.y;
+                acc[jj].y += v.x * c.y + v.y * c.x;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < CJ; jj++)
+            if (j0 + jj < no) O[(long)(j0 + jj) * ldo + idx] = acc[jj];
+    }
+}
+
+hipError_t launch_combine(const double2 *V, long ldv, int nv, const double2 *C_dev, int ldc, double2 *O, long ldo,
+                          int no, long n, hipStream_t s) {
+    if (nv > 128) return hipErrorInvalidValue;
+    const int gx = 1024;
+    hipLaunchKernelGGL(k_combine, dim3(gx, (no + CJ - 1) / CJ), dim3(256), 0, s, V, ldv, nv, C_dev, ldc, O, ldo, no,
+                       n);
+    return hipGetLastError();
+}
+
+// y = a x + b y + c z over n reals (z may be null when c == 0)
+template <class R>
+__global__ void k_lincomb(long n, R a, const R *__restrict__ x, R b, R *__restrict__ y, R c, const R *__restrict__ z) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        R v = a * x[i] + b * y[i];
+        if (z) v += c * z[i];
+        y[i] = v;
+    }
+}
+
+hipError_t launch_lincomb64(long nreal, double a, const double *x, double b, double *y, double c, const double *z,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb<double>, dim3(2048), dim3(256), 0, s, nreal, a, x, b, y, c, z);
+    return hipGetLastError();
+}
+hipError_t launch_lincomb32(long nreal, float a, const float *x, float b, float *y, float c, const float *z,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb<float>, dim3(2048), dim3(256), 0, s, nreal, a, x, b, y, c, z);
+    return hipGetLastError();
+}
+
+// FP64 native double2 [p][12][Vh][2]  <->  FP32 native float4 [p][6][Vh][2]
+__global__ void k_convert(long nsite2, int Vh, int nvec, const double2 *__restrict__ d, float4 *__restrict__ f,
+                          int to64, double2 *__restrict__ d_out, const float4 *__restrict__ f_in) {
+    // one thread per (vector, parity, component pair, site-in-parity, copy)
+    const long total = (long)nvec * 2 * 6 * Vh * 2;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        long r = e;
+        const int c = r & 1;
+        r >>= 1;
+        const long h = r % Vh;
+        r /= Vh;
+        const int k2 = r % 6;
+        r /= 6;
+        const int p = r % 2;
+        const long v = r / 2;
+        const long base64 = v * nsite2 * 12;
+        const long i0 = base64 + (((long)(p * 12 + 2 * k2) * Vh + h) * 2 + c);
+        const long i1 = base64 + (((long)(p * 12 + 2 * k2 + 1) * Vh + h) * 2 + c);
+        const long i32 = v * nsite2 * 6 + (((long)(p * 6 + k2) * Vh + h) * 2 + c);
+        if (!to64) {
+            const double2 a = d[i0], b = d[i1];
+            f[i32] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        } else {
+            const float4 q = f_in[i32];
+            d_out[i0] = make_double2(q.x, q.y);
+            d_out[i1] = make_double2(q.z, q.w);
+        }
+    }
+}
+
+hipError_t launch_to_f32(const Geo &g, int nvec, const double2 *src, float4 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert, dim3(4096), dim3(256), 0, s, 4L * g.Vh, g.Vh, nvec, src, dst, 0, nullptr,
+                       nullptr);
+    return hipGetLastError();
+}
+hipError_t launch_to_f64(const Geo &g, int nvec, const float4 *src, double2 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert, dim3(4096), dim3(256), 0, s, 4L * g.Vh, g.Vh, nvec, nullptr, nullptr, 1, dst, src);
+    return hipGetLastError();
+}
+
+// Gaussian complex entries from a counter-based hash (splitmix64 finaliser) + Box-Muller.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ void k_gauss(double2 *__restrict__ x, long n, unsigned long long seed) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const unsigned long long a = mix64(seed ^ mix64(2 * (unsigned long long)i));
+        const unsigned long long b = mix64(seed ^ mix64(2 * (unsigned long long)i + 1));
+        const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+        const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+        const double r = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        x[i] = make_double2(r * cs, r * sn);
+    }
+}
+hipError_t launch_gauss(double2 *x, long n, unsigned long long seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_gauss, dim3(2048), dim3(256), 0, s, x, n, seed);
+    return hipGetLastError();
+}
+
+}  // namespace cstar

@@ -1,0 +1,813 @@
+// HIP kernels of the C* Wilson-clover operator for gfx950.
+//
+//  * link packing: physical SU(3) x U(1) links -> FP64 quark links, FP32 / BF16
+//    compressed rows with the quark phase exp(i q theta) as an FP32 (cos, sin) pair;
+//  * clover: field strength from the four plaquette leaves on the x-doubled
+//    lattice, SW = (i/4) sigma_{mu nu} F_{mu nu} as two Hermitian 6x6 blocks
+//    (the term commutes with g5) for the physical copy of every site;
+//  * apply: one thread per site of the x-doubled lattice, the two copies of a
+//    physical site in adjacent lanes so that both read the same link and
+//    clover words in one wave; spin projection of every hop (rank-2 (1-+g_mu)).
+//
+// Operator (paper, sign-of-the-Pfaffian and setup sections; chiral basis with
+// g0 = [[0,-1],[-1,0]], gk = [[0,-i s_k],[i s_k,0]], g5 = diag(1,1,-1,-1)):
+//   (D psi)(x) = (4+m) psi(x) + SW(x) psi(x)
+//              - 1/2 sum_mu [(1-g_mu) V(x,mu) psi(x+mu) + (1+g_mu) V(x-mu,mu)^H psi(x-mu)].
+// C* on the doubled lattice: the copy of x at x1+L sees conj(U), -theta; a hop
+// that leaves [0,L) in x1, x2 or x3 lands on the other copy.
+#include "cstar_internal.h"
+
+namespace cstar {
+
+template <class R>
+struct cx {
+    R re, im;
+};
+template <class R>
+__device__ __forceinline__ cx<R> mk(R a, R b) { return {a, b}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R>
+__device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R>
+__device__ __forceinline__ cx<R> conjmul(cx<R> a, cx<R> b) {  // conj(a) * b
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class R>
+__device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
+template <class R>
+__device__ __forceinline__ cx<R> mul_mi(cx<R> a) { return {a.im, -a.re}; }
+template <class R>
+__device__ __forceinline__ cx<R> cj(cx<R> a) { return {a.re, -a.im}; }
+
+// ---------------------------------------------------------------- geometry
+__device__ __forceinline__ void decode(const Geo &g, int p, int h, int &t, int &x1, int &x2, int &x3) {
+    int r = h;
+    const int x3h = r % g.Lh;
+    r /= g.Lh;
+    x2 = r % g.L;
+    r /= g.L;
+    x1 = r % g.L;
+    t = r / g.L;
+    x3 = 2 * x3h + ((p + t + x1 + x2) & 1);
+}
+__device__ __forceinline__ int pair_index(const Geo &g, int t, int x1, int x2, int x3) {
+    return (((t * g.L + x1) * g.L + x2) * g.L + x3) >> 1;
+}
+
+struct Hop {
+    int h;     // in-parity index of the neighbour pair (parity 1-p)
+    int flip;  // 1 if the hop lands on the other copy (C* wrap)
+    int tw;    // 1 if the hop wraps in time
+};
+
+template <int MU>
+__device__ __forceinline__ Hop hop_fwd(const Geo &g, int t, int x1, int x2, int x3) {
+    int flip = 0, tw = 0;
+    if (MU == 0) { t += 1; if (t == g.T) { t = 0; tw = 1; } }
+    if (MU == 1) { x1 += 1; if (x1 == g.L) { x1 = 0; flip = 1; } }
+    if (MU == 2) { x2 += 1; if (x2 == g.L) { x2 = 0; flip = 1; } }
+    if (MU == 3) { x3 += 1; if (x3 == g.L) { x3 = 0; flip = 1; } }
+    return {pair_index(g, t, x1, x2, x3), flip, tw};
+}
+template <int MU>
+__device__ __forceinline__ Hop hop_bwd(const Geo &g, int t, int x1, int x2, int x3) {
+    int flip = 0, tw = 0;
+    if (MU == 0) { if (t == 0) { t = g.T; tw = 1; } t -= 1; }
+    if (MU == 1) { if (x1 == 0) { x1 = g.L; flip = 1; } x1 -= 1; }
+    if (MU == 2) { if (x2 == 0) { x2 = g.L; flip = 1; } x2 -= 1; }
+    if (MU == 3) { if (x3 == 0) { x3 = g.L; flip = 1; } x3 -= 1; }
+    return {pair_index(g, t, x1, x2, x3), flip, tw};
+}
+
+// ---------------------------------------------------------------- spinor storage
+// FP64: double2 [p][12][Vh][2];  FP32: float4 [p][6][Vh][2]
+template <class R>
+struct SpinorIO;
+
+template <>
+struct SpinorIO<double> {
+    using vec = double2;
+    static __device__ __forceinline__ void load(const double2 *__restrict__ b, const Geo &g, int p, int h, int c,
+                                                cx<double> v[12]) {
+        const double2 *q = b + ((long)p * 12 * g.Vh + h) * 2 + c;
+        const long st = 2L * g.Vh;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double2 w = q[k * st];
+            v[k] = {w.x, w.y};
+        }
+    }
+    static __device__ __forceinline__ void store(double2 *__restrict__ b, const Geo &g, int p, int h, int c,
+                                                 const cx<double> v[12]) {
+        double2 *q = b + ((long)p * 12 * g.Vh + h) * 2 + c;
+        const long st = 2L * g.Vh;
+#pragma unroll
+        for (int k = 0; k < 12; k++) q[k * st] = make_double2(v[k].re, v[k].im);
+    }
+};
+
+template <>
+struct SpinorIO<float> {
+    using vec = float4;
+    static __device__ __forceinline__ void load(const float4 *__restrict__ b, const Geo &g, int p, int h, int c,
+                                                cx<float> v[12]) {
+        const float4 *q = b + ((long)p * 6 * g.Vh + h) * 2 + c;
+        const long st = 2L * g.Vh;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const float4 w = q[k * st];
+            v[2 * k] = {w.x, w.y};
+            v[2 * k + 1] = {w.z, w.w};
+        }
+    }
+    static __device__ __forceinline__ void store(float4 *__restrict__ b, const Geo &g, int p, int h, int c,
+                                                 const cx<float> v[12]) {
+        float4 *q = b + ((long)p * 6 * g.Vh + h) * 2 + c;
+        const long st = 2L * g.Vh;
+#pragma unroll
+        for (int k = 0; k < 6; k++) q[k * st] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+};
+
+// ---------------------------------------------------------------- links
+// A link as used by one lane: U (3x3, possibly conjugated) and a phase e^{i phi}
+// that multiplies the matrix-vector product (forward) or its conjugate (adjoint).
+template <class R>
+struct Link {
+    cx<R> u[9];
+    cx<R> ph;
+};
+
+__device__ __forceinline__ float bf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <class R>
+__device__ __forceinline__ void row2_from_rows(cx<R> u[9]) {
+    // row 2 = conj(row0 x row1)
+    u[6] = cj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = cj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = cj(u[0] * u[4] - u[1] * u[3]);
+}
+
+struct FmtF64 {
+    using R = double;
+    static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int mu, int h, double s,
+                                                Link<double> &L) {
+        const double2 *b = d.link64 + (long)(p * 4 + mu) * 9 * g.Vh + h;
+#pragma unroll
+        for (int r = 0; r < 9; r++) {
+            const double2 w = b[(long)r * g.Vh];
+            L.u[r] = {w.x, s * w.y};
+        }
+        L.ph = {1.0, 0.0};
+    }
+    static constexpr bool has_phase = false;
+};
+
+struct FmtF32 {
+    using R = float;
+    static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int mu, int h, float s,
+                                                Link<float> &L) {
+        const float4 *b = d.link32 + (long)(p * 4 + mu) * 3 * g.Vh + h;
+        const float4 a0 = b[0], a1 = b[g.Vh], a2 = b[2 * (long)g.Vh];
+        L.u[0] = {a0.x, s * a0.y};
+        L.u[1] = {a0.z, s * a0.w};
+        L.u[2] = {a1.x, s * a1.y};
+        L.u[3] = {a1.z, s * a1.w};
+        L.u[4] = {a2.x, s * a2.y};
+        L.u[5] = {a2.z, s * a2.w};
+        row2_from_rows(L.u);
+        const float2 e = d.phase32[(long)(p * 4 + mu) * g.Vh + h];
+        L.ph = {e.x, s * e.y};
+    }
+    static constexpr bool has_phase = true;
+};
+
+struct FmtBF16 {
+    using R = float;
+    static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int mu, int h, float s,
+                                                Link<float> &L) {
+        const long i = (long)(p * 4 + mu) * g.Vh + h;
+        const uint4 a = d.linkbf_a[i];
+        const uint2 b = d.linkbf_b[i];
+        L.u[0] = {bf_lo(a.x), s * bf_hi(a.x)};
+        L.u[1] = {bf_lo(a.y), s * bf_hi(a.y)};
+        L.u[2] = {bf_lo(a.z), s * bf_hi(a.z)};
+        L.u[3] = {bf_lo(a.w), s * bf_hi(a.w)};
+        L.u[4] = {bf_lo(b.x), s * bf_hi(b.x)};
+        L.u[5] = {bf_lo(b.y), s * bf_hi(b.y)};
+        row2_from_rows(L.u);
+        const float2 e = d.phase32[i];
+        L.ph = {e.x, s * e.y};
+    }
+    static constexpr bool has_phase = true;
+};
+
+// g = V h (DAG = false) or V^H h (DAG = true) for the two spin rows of a half spinor.
+template <class Fmt, bool DAG, class R>
+__device__ __forceinline__ void link_mul(const Link<R> &L, const cx<R> h[6], cx<R> o[6]) {
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            cx<R> acc = {R(0), R(0)};
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                if (DAG)
+                    acc = acc + conjmul(L.u[j * 3 + i], h[s * 3 + j]);
+                else
+                    acc = acc + L.u[i * 3 + j] * h[s * 3 + j];
+            }
+            if (Fmt::has_phase) acc = DAG ? conjmul(L.ph, acc) : L.ph * acc;
+            o[s * 3 + i] = acc;
+        }
+    }
+}
+
+// Spin projection: h = P psi for (1 + SG*g_mu) (SG = -1 forward hop, +1 backward hop),
+// and reconstruction of the full 4-spinor from the transported half spinor.
+template <int MU, int SG, class R>
+__device__ __forceinline__ void project(const cx<R> v[12], cx<R> h[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const cx<R> p0 = v[a], p1 = v[3 + a], p2 = v[6 + a], p3 = v[9 + a];
+        if (MU == 0) {
+            h[a] = SG < 0 ? p0 + p2 : p0 - p2;
+            h[3 + a] = SG < 0 ? p1 + p3 : p1 - p3;
+        } else if (MU == 1) {
+            h[a] = SG < 0 ? p0 + mul_i(p3) : p0 - mul_i(p3);
+            h[3 + a] = SG < 0 ? p1 + mul_i(p2) : p1 - mul_i(p2);
+        } else if (MU == 2) {
+            h[a] = SG < 0 ? p0 + p3 : p0 - p3;
+            h[3 + a] = SG < 0 ? p1 - p2 : p1 + p2;
+        } else {
+            h[a] = SG < 0 ? p0 + mul_i(p2) : p0 - mul_i(p2);
+            h[3 + a] = SG < 0 ? p1 - mul_i(p3) : p1 + mul_i(p3);
+        }
+    }
+}
+
+// acc += f * (1 + SG g_mu)-reconstruction of the transported half spinor g
+template <int MU, int SG, class R>
+__device__ __forceinline__ void accumulate(cx<R> acc[12], const cx<R> g[6], R f) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const cx<R> g0 = scale(g[a], f), g1 = scale(g[3 + a], f);
+        acc[a] = acc[a] + g0;
+        acc[3 + a] = acc[3 + a] + g1;
+        cx<R> r2, r3;
+        if (MU == 0) {
+            r2 = SG < 0 ? g0 : mk(-g0.re, -g0.im);
+            r3 = SG < 0 ? g1 : mk(-g1.re, -g1.im);
+        } else if (MU == 1) {
+            r2 = SG < 0 ? mul_mi(g1) : mul_i(g1);
+            r3 = SG < 0 ? mul_mi(g0) : mul_i(g0);
+        } else if (MU == 2) {
+            r2 = SG < 0 ? mk(-g1.re, -g1.im) : g1;
+            r3 = SG < 0 ? g0 : mk(-g0.re, -g0.im);
+        } else {
+            r2 = SG < 0 ? mul_mi(g0) : mul_i(g0);
+            r3 = SG < 0 ? mul_i(g1) : mul_mi(g1);
+        }
+        acc[6 + a] = acc[6 + a] + r2;
+        acc[9 + a] = acc[9 + a] + r3;
+    }
+}
+
+// ---------------------------------------------------------------- clover storage
+// Block b (b=0: spins 0,1; b=1: spins 2,3) of the Hermitian 6x6 term, index
+// i = 3*spin_in_block + colour: 6 real diagonal entries, then the 15 strictly
+// lower entries M[i][j] (i > j) in row order, off(i,j) = i(i-1)/2 + j.
+template <class R>
+struct CloverIO;
+
+template <>
+struct CloverIO<double> {
+    static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int h, int b, double dg[6],
+                                                cx<double> o[15]) {
+        const double2 *q = d.clov64 + (long)(p * 36 + b * 18) * g.Vh + h;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const double2 w = q[(long)k * g.Vh];
+            dg[2 * k] = w.x;
+            dg[2 * k + 1] = w.y;
+        }
+#pragma unroll
+        for (int k = 0; k < 15; k++) {
+            const double2 w = q[(long)(3 + k) * g.Vh];
+            o[k] = {w.x, w.y};
+        }
+    }
+};
+template <>
+struct CloverIO<float> {
+    static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int h, int b, float dg[6],
+                                                cx<float> o[15]) {
+        const float4 *q = d.clov32 + (long)(p * 18 + b * 9) * g.Vh + h;
+        const float4 w0 = q[0], w1 = q[g.Vh];
+        dg[0] = w0.x; dg[1] = w0.y; dg[2] = w0.z; dg[3] = w0.w;
+        dg[4] = w1.x; dg[5] = w1.y;
+        o[0] = {w1.z, w1.w};
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            const float4 w = q[(long)(2 + k) * g.Vh];
+            o[1 + 2 * k] = {w.x, w.y};
+            o[2 + 2 * k] = {w.z, w.w};
+        }
+    }
+};
+
+template <class R>
+__device__ __forceinline__ void herm6_mul(const R dg[6], const cx<R> o[15], const cx<R> u[6], cx<R> w[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        cx<R> acc = scale(u[i], dg[i]);
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            if (j < i) acc = acc + o[i * (i - 1) / 2 + j] * u[j];
+            if (j > i) acc = acc + conjmul(o[j * (j - 1) / 2 + i], u[j]);
+        }
+        w[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- apply kernel
+template <class Fmt>
+struct Prec;
+template <>
+struct Prec<FmtF64> {
+    using R = double;
+    using V = double2;
+};
+template <>
+struct Prec<FmtF32> {
+    using R = float;
+    using V = float4;
+};
+template <>
+struct Prec<FmtBF16> {
+    using R = float;
+    using V = float4;
+};
+
+template <class Fmt, int MU>
+__device__ __forceinline__ void hop_pair(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
+                                         int p, int h, int c, int t, int x1, int x2, int x3,
+                                         cx<typename Prec<Fmt>::R> acc[12]) {
+    using R = typename Prec<Fmt>::R;
+    const R half = R(-0.5);
+    {  // forward: -1/2 (1 - g_mu) V(x,mu) psi(x+mu)
+        const Hop n = hop_fwd<MU>(g, t, x1, x2, x3);
+        Link<R> L;
+        Fmt::load(d, g, p, MU, h, c ? R(-1) : R(1), L);
+        cx<R> v[12], hh[6], gg[6];
+        SpinorIO<R>::load(in, g, 1 - p, n.h, c ^ n.flip, v);
+        project<MU, -1>(v, hh);
+        link_mul<Fmt, false>(L, hh, gg);
+        const R f = (n.tw && g.time_bc < 0) ? -half : half;
+        accumulate<MU, -1>(acc, gg, f);
+    }
+    {  // backward: -1/2 (1 + g_mu) V(x-mu,mu)^H psi(x-mu)
+        const Hop n = hop_bwd<MU>(g, t, x1, x2, x3);
+        const int cn = c ^ n.flip;
+        Link<R> L;
+        Fmt::load(d, g, 1 - p, MU, n.h, cn ? R(-1) : R(1), L);
+        cx<R> v[12], hh[6], gg[6];
+        SpinorIO<R>::load(in, g, 1 - p, n.h, cn, v);
+        project<MU, 1>(v, hh);
+        link_mul<Fmt, true>(L, hh, gg);
+        const R f = (n.tw && g.time_bc < 0) ? -half : half;
+        accumulate<MU, 1>(acc, gg, f);
+    }
+}
+
+// Clover term of one lane: the physical copy uses the stored blocks M; the
+// conjugate copy uses sigma2 M^* sigma2 (its field strength is conj(F)),
+// evaluated as -sigma2 conj(M sigma2 chi^*) in each chirality block.
+template <class R>
+__device__ __forceinline__ void clover_add(const GaugeDev &d, const Geo &g, int p, int h, int c, const cx<R> chi[12],
+                                           cx<R> acc[12]) {
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        R dg[6];
+        cx<R> o[15];
+        CloverIO<R>::load(d, g, p, h, b, dg, o);
+        cx<R> u[6], w[6];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const cx<R> c0 = chi[6 * b + a], c1 = chi[6 * b + 3 + a];
+            u[a] = c ? mk(-c1.im, -c1.re) : c0;      // -i conj(chi1)
+            u[3 + a] = c ? mk(c0.im, c0.re) : c1;    //  i conj(chi0)
+        }
+        herm6_mul(dg, o, u, w);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const cx<R> r0 = c ? mk(w[3 + a].im, w[3 + a].re) : w[a];     //  i conj(w1)
+            const cx<R> r1 = c ? mk(-w[a].im, -w[a].re) : w[3 + a];       // -i conj(w0)
+            acc[6 * b + a] = acc[6 * b + a] + r0;
+            acc[6 * b + 3 + a] = acc[6 * b + 3 + a] + r1;
+        }
+    }
+}
+
+// Materialise the accumulator at this point of the program: the arithmetic of
+// the hops before it cannot sink below it, which bounds the live registers to
+// one direction's loads instead of all sixteen hops' (the default schedule
+// loads everything first and spills).
+template <class R>
+__device__ __forceinline__ void pin(cx<R> acc[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+}
+
+// One site of the x-doubled lattice (lane = pair x copy), one right-hand side.
+template <class Fmt>
+__device__ __forceinline__ void site_apply(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
+                                           typename Prec<Fmt>::V *__restrict__ out, int p, int h, int c, int t, int x1,
+                                           int x2, int x3, double mass, int gamma5) {
+    using R = typename Prec<Fmt>::R;
+    cx<R> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {R(0), R(0)};
+    // scheduling fences between directions bound the live loads (and registers)
+    // to one direction's two hops
+    hop_pair<Fmt, 0>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    pin(acc);
+    hop_pair<Fmt, 1>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    pin(acc);
+    hop_pair<Fmt, 2>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    pin(acc);
+    hop_pair<Fmt, 3>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    pin(acc);
+    cx<R> chi[12];
+    SpinorIO<R>::load(in, g, p, h, c, chi);
+    clover_add<R>(d, g, p, h, c, chi, acc);
+    const R dm = R(4.0 + mass);
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = acc[k] + scale(chi[k], dm);
+    if (gamma5) {
+#pragma unroll
+        for (int k = 6; k < 12; k++) acc[k] = mk(-acc[k].re, -acc[k].im);
+    }
+    SpinorIO<R>::store(out, g, p, h, c, acc);
+}
+
+// Occupancy target of the apply kernels: FP32 forms at <= 128 VGPRs (4 waves
+// per SIMD), FP64 at <= 256.
+template <class Fmt>
+struct Occ {
+    static constexpr int waves = 4;
+};
+template <>
+struct Occ<FmtF64> {
+    static constexpr int waves = 2;
+};
+
+// One launch for nrhs right-hand sides (each with its own mass).  Workgroup
+// w of the launch is mapped to the logical item (tile, rhs) so that the eight
+// XCDs each own a contiguous range of tiles with all their right-hand sides:
+// the hardware hands out workgroups round-robin over the XCDs (w mod 8), and
+// each XCD has its own L2, so the link and clover words of a tile -- and the
+// neighbour spinors shared between adjacent tiles -- are fetched from HBM once
+// per XCD instead of once per right-hand side.
+template <class Fmt>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::waves))) void k_apply(
+    Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
+    long stride, int nrhs, int ntiles, int gamma5, const double *__restrict__ masses, double mass0) {
+    const int nwg = gridDim.x;  // a multiple of 8
+    const int w = blockIdx.x;
+    const int logical = (w & 7) * (nwg >> 3) + (w >> 3);
+    if (logical >= ntiles * nrhs) return;
+    const int tile = logical / nrhs;
+    const int j = logical - tile * nrhs;
+    const int gid = tile * 256 + threadIdx.x;
+    if (gid >= 4 * g.Vh) return;
+    const int c = gid & 1;
+    const int pair = gid >> 1;
+    const int p = pair >= g.Vh;
+    const int h = pair - p * g.Vh;
+    int t, x1, x2, x3;
+    decode(g, p, h, t, x1, x2, x3);
+    const double m = masses ? masses[j] : mass0;
+    site_apply<Fmt>(g, d, in + j * stride, out + j * stride, p, h, c, t, x1, x2, x3, m, gamma5);
+}
+
+template <class Fmt>
+static void launch_apply_t(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
+    using V = typename Prec<Fmt>::V;
+    const int ntiles = (4 * g.Vh + 255) / 256;
+    const long items = (long)ntiles * a.nrhs;
+    const int nwg = (int)((items + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_apply<Fmt>, dim3(nwg), dim3(256), 0, s, g, d, (const V *)a.in, (V *)a.out,
+                       a.stride / (long)sizeof(V), a.nrhs, ntiles, a.gamma5, a.masses_dev, a.mass0);
+}
+
+hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s) {
+    if (prec == CSTAR_FP64)
+        launch_apply_t<FmtF64>(g, d, a, s);
+    else if (prec == CSTAR_FP32)
+        launch_apply_t<FmtF32>(g, d, a, s);
+    else
+        launch_apply_t<FmtBF16>(g, d, a, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- link packing
+__device__ __forceinline__ unsigned bf16_bits(double v) {
+    // FP64 -> nearest FP32 -> round-to-nearest-even on the upper 16 bits
+    const unsigned u = __float_as_uint((float)v);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ unsigned bf16_pair(double lo, double hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+
+__global__ void k_pack_links(Geo g, const double *__restrict__ su3, const double *__restrict__ theta, double q,
+                             GaugeDev d) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 2 * g.Vh * 4) return;
+    const int mu = gid & 3;
+    const int pair = gid >> 2;
+    const int p = pair >= g.Vh;
+    const int h = pair - p * g.Vh;
+    int t, x1, x2, x3;
+    decode(g, p, h, t, x1, x2, x3);
+    const long lex = ((long)(t * g.L + x1) * g.L + x2) * g.L + x3;
+    const double *u = su3 + (lex * 4 + mu) * 18;
+    const double th = theta[lex * 4 + mu];
+    const double phi = q * th;
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    const long base9 = (long)(p * 4 + mu) * 9;
+    for (int r = 0; r < 9; r++) {
+        const double re = u[2 * r], im = u[2 * r + 1];
+        d.link64[(base9 + r) * g.Vh + h] = make_double2(cs * re - sn * im, cs * im + sn * re);
+    }
+    const long base3 = (long)(p * 4 + mu) * 3;
+    for (int k = 0; k < 3; k++)
+        d.link32[(base3 + k) * g.Vh + h] = make_float4((float)u[4 * k], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                                                       (float)u[4 * k + 3]);
+    const long i = (long)(p * 4 + mu) * g.Vh + h;
+    d.linkbf_a[i] = make_uint4(bf16_pair(u[0], u[1]), bf16_pair(u[2], u[3]), bf16_pair(u[4], u[5]),
+                               bf16_pair(u[6], u[7]));
+    d.linkbf_b[i] = make_uint2(bf16_pair(u[8], u[9]), bf16_pair(u[10], u[11]));
+    d.phase32[i] = make_float2((float)cs, (float)sn);
+}
+
+hipError_t launch_pack_links(const Geo &g, const double *su3, const double *theta, double q, GaugeDev &d,
+                             hipStream_t s) {
+    const int n = 2 * g.Vh * 4;
+    hipLaunchKernelGGL(k_pack_links, dim3((n + 255) / 256), dim3(256), 0, s, g, su3, theta, q, d);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- clover
+// A point of the doubled lattice in pair form: physical coordinates + copy index.
+struct Pt {
+    int t, x1, x2, x3, c;
+};
+
+__device__ __forceinline__ Pt step(const Geo &g, Pt a, int mu, int dir) {
+    int *x = mu == 0 ? &a.t : mu == 1 ? &a.x1 : mu == 2 ? &a.x2 : &a.x3;
+    const int ext = mu == 0 ? g.T : g.L;
+    *x += dir;
+    if (*x == ext || *x < 0) {
+        *x = (*x + ext) % ext;
+        if (mu) a.c ^= 1;
+    }
+    return a;
+}
+
+// U_e(a, mu) with its U(1) angle on the doubled lattice
+__device__ __forceinline__ void load_link64(const Geo &g, const double *su3, const double *theta, Pt a, int mu,
+                                            cx<double> U[9], double &th) {
+    const long lex = ((long)(a.t * g.L + a.x1) * g.L + a.x2) * g.L + a.x3;
+    const double *u = su3 + (lex * 4 + mu) * 18;
+    const double s = a.c ? -1.0 : 1.0;
+#pragma unroll
+    for (int r = 0; r < 9; r++) U[r] = {u[2 * r], s * u[2 * r + 1]};
+    th = s * theta[lex * 4 + mu];
+}
+
+__device__ __forceinline__ void mm3(const cx<double> A[9], const cx<double> B[9], cx<double> C[9]) {
+    cx<double> r[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; k++) s = s + A[i * 3 + k] * B[k * 3 + j];
+            r[i * 3 + j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < 9; i++) C[i] = r[i];
+}
+__device__ __forceinline__ void mm3_dag_right(const cx<double> A[9], const cx<double> B[9], cx<double> C[9]) {
+    // C = A * B^H
+    cx<double> r[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; k++) s = s + A[i * 3 + k] * cj(B[j * 3 + k]);
+            r[i * 3 + j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < 9; i++) C[i] = r[i];
+}
+
+// Plaquette leaf starting and ending at x: the loop x -> x+s1 -> ... with
+// signed unit steps (mu first, then nu for the same orientation).
+__device__ void leaf(const Geo &g, const double *su3, const double *theta, Pt x, const int steps[4], cx<double> P[9],
+                     double &ang) {
+#pragma unroll
+    for (int i = 0; i < 9; i++) P[i] = {0.0, 0.0};
+    P[0] = P[4] = P[8] = {1.0, 0.0};
+    ang = 0.0;
+    Pt y = x;
+    for (int k = 0; k < 4; k++) {
+        const int mu = (steps[k] > 0 ? steps[k] : -steps[k]) - 1;
+        cx<double> U[9];
+        double th;
+        if (steps[k] > 0) {
+            load_link64(g, su3, theta, y, mu, U, th);
+            mm3(P, U, P);
+            ang += th;
+            y = step(g, y, mu, +1);
+        } else {
+            y = step(g, y, mu, -1);
+            load_link64(g, su3, theta, y, mu, U, th);
+            mm3_dag_right(P, U, P);
+            ang -= th;
+        }
+    }
+}
+
+// One thread per physical site: F_{mu nu} for the six planes, the two
+// chirality blocks of (i/2) sum_{mu<nu} sigma_{mu nu} F_{mu nu} in closed
+// form for this basis:
+//   sigma_{0k} = diag(s_k, -s_k),  sigma_{jk} = -eps_{jkl} diag(s_l, s_l),
+//   block(X) = (i/2) [[X3, X1 - i X2], [X1 + i X2, -X3]],
+//   upper X = (F01 - F23, F02 + F13, F03 - F12), lower X = (-F01 - F23, -F02 + F13, -F03 - F12).
+__global__ void k_clover(Geo g, const double *__restrict__ su3, const double *__restrict__ theta, double q,
+                         double csw_su3, double csw_u1, GaugeDev d, double *__restrict__ norm_partial) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0.0;
+    if (gid < 2 * g.Vh) {
+        const int p = gid >= g.Vh;
+        const int h = gid - p * g.Vh;
+        Pt x;
+        decode(g, p, h, x.t, x.x1, x.x2, x.x3);
+        x.c = 0;
+        cx<double> F[6][9];
+        const int planes[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        for (int pl = 0; pl < 6; pl++) {
+            const int a = planes[pl][0] + 1, b = planes[pl][1] + 1;
+            const int lv[4][4] = {{a, b, -a, -b}, {b, -a, -b, a}, {-a, -b, a, b}, {-b, a, b, -a}};
+            cx<double> Qs[9];
+            for (int i = 0; i < 9; i++) Qs[i] = {0.0, 0.0};
+            double ssum = 0.0;
+            for (int l = 0; l < 4; l++) {
+                cx<double> P[9];
+                double ang;
+                leaf(g, su3, theta, x, lv[l], P, ang);
+                for (int i = 0; i < 9; i++) Qs[i] = Qs[i] + P[i];
+                ssum += sin(ang);
+            }
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    // (Q - Q^H)/8
+                    const cx<double> qij = Qs[i * 3 + j], qji = Qs[j * 3 + i];
+                    cx<double> f = {csw_su3 * (qij.re - qji.re) / 8.0, csw_su3 * (qij.im + qji.im) / 8.0};
+                    if (i == j) f.im += q * csw_u1 * 0.25 * ssum;
+                    F[pl][i * 3 + j] = f;
+                }
+        }
+        for (int blk = 0; blk < 2; blk++) {
+            const double s0 = blk == 0 ? 1.0 : -1.0;
+            cx<double> X[3][9];
+            for (int i = 0; i < 9; i++) {
+                X[0][i] = scale(F[0][i], s0) - F[5][i];
+                X[1][i] = scale(F[1][i], s0) + F[4][i];
+                X[2][i] = scale(F[2][i], s0) - F[3][i];
+            }
+            // M (6x6), index s*3 + colour; M = (i/2) [[X3, X1 - i X2],[X1 + i X2, -X3]]
+            cx<double> M[6][6];
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) {
+                    const cx<double> x1v = X[0][i * 3 + j], x2v = X[1][i * 3 + j], x3v = X[2][i * 3 + j];
+                    M[i][j] = scale(mul_i(x3v), 0.5);
+                    M[3 + i][3 + j] = scale(mul_i(x3v), -0.5);
+                    M[i][3 + j] = scale(mul_i(x1v - mul_i(x2v)), 0.5);
+                    M[3 + i][j] = scale(mul_i(x1v + mul_i(x2v)), 0.5);
+                }
+            double rowsum_max = 0.0, frob = 0.0;
+            for (int i = 0; i < 6; i++) {
+                double rs = 0.0;
+                for (int j = 0; j < 6; j++) {
+                    const double m2 = M[i][j].re * M[i][j].re + M[i][j].im * M[i][j].im;
+                    rs += sqrt(m2);
+                    frob += m2;
+                }
+                rowsum_max = fmax(rowsum_max, rs);
+            }
+            nrm = fmax(nrm, fmin(rowsum_max, sqrt(frob)));
+            double2 *q64 = d.clov64 + (long)(p * 36 + blk * 18) * g.Vh + h;
+            float *tmp = nullptr;
+            (void)tmp;
+            double re36[36];
+            for (int i = 0; i < 6; i++) re36[i] = M[i][i].re;
+            for (int i = 1; i < 6; i++)
+                for (int j = 0; j < i; j++) {
+                    const int k = i * (i - 1) / 2 + j;
+                    re36[6 + 2 * k] = M[i][j].re;
+                    re36[7 + 2 * k] = M[i][j].im;
+                }
+            for (int k = 0; k < 18; k++) q64[(long)k * g.Vh] = make_double2(re36[2 * k], re36[2 * k + 1]);
+            float4 *q32 = d.clov32 + (long)(p * 18 + blk * 9) * g.Vh + h;
+            for (int k = 0; k < 9; k++)
+                q32[(long)k * g.Vh] = make_float4((float)re36[4 * k], (float)re36[4 * k + 1], (float)re36[4 * k + 2],
+                                                  (float)re36[4 * k + 3]);
+        }
+    }
+    // block max of the per-site norm bound
+    __shared__ double red[256];
+    red[threadIdx.x] = nrm;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norm_partial[blockIdx.x] = red[0];
+}
+
+int clover_norm_blocks(const Geo &g) { return (2 * g.Vh + 255) / 256; }
+
+hipError_t launch_clover(const Geo &g, const double *su3, const double *theta, double q, double csw_su3,
+                         double csw_u1, GaugeDev &d, double *norm_partial, hipStream_t s) {
+    hipLaunchKernelGGL(k_clover, dim3(clover_norm_blocks(g)), dim3(256), 0, s, g, su3, theta, q, csw_su3, csw_u1, d,
+                       norm_partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- layout conversion
+// canonical [T][2L][L][L][4][3] complex  <->  native (see cstar.h)
+template <class R>
+__global__ void k_pack_spinor(Geo g, const void *__restrict__ src, void *__restrict__ dst, int nrhs, int unpack) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 4 * g.Vh) return;
+    const int c = gid & 1;
+    const int pair = gid >> 1;
+    const int p = pair >= g.Vh;
+    const int h = pair - p * g.Vh;
+    int t, x1, x2, x3;
+    decode(g, p, h, t, x1, x2, x3);
+    const long site = ((long)(t * 2 * g.L + x1 + c * g.L) * g.L + x2) * g.L + x3;
+    const long nsite = 4L * g.Vh;
+    using V = typename SpinorIO<R>::vec;
+    const long nvec = (long)(sizeof(R) == 8 ? 12 : 6) * nsite;  // native vector entries per rhs
+    for (int j = 0; j < nrhs; j++) {
+        cx<R> v[12];
+        if (!unpack) {
+            const cx<R> *s = (const cx<R> *)src + (j * nsite + site) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[k] = s[k];
+            SpinorIO<R>::store((V *)dst + j * nvec, g, p, h, c, v);
+        } else {
+            SpinorIO<R>::load((const V *)src + j * nvec, g, p, h, c, v);
+            cx<R> *s = (cx<R> *)dst + (j * nsite + site) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; k++) s[k] = v[k];
+        }
+    }
+}
+
+hipError_t launch_pack_spinor(const Geo &g, cstar_prec prec, int nrhs, void *canon, void *native, int unpack,
+                              hipStream_t s) {
+    const int n = 4 * g.Vh;
+    const dim3 grd((n + 255) / 256), blk(256);
+    if (prec == CSTAR_FP64) {
+        if (!unpack)
+            hipLaunchKernelGGL(k_pack_spinor<double>, grd, blk, 0, s, g, canon, native, nrhs, 0);
+        else
+            hipLaunchKernelGGL(k_pack_spinor<double>, grd, blk, 0, s, g, (const void *)native, (void *)canon, nrhs, 1);
+    } else {
+        if (!unpack)
+            hipLaunchKernelGGL(k_pack_spinor<float>, grd, blk, 0, s, g, canon, native, nrhs, 0);
+        else
+            hipLaunchKernelGGL(k_pack_spinor<float>, grd, blk, 0, s, g, (const void *)native, (void *)canon, nrhs, 1);
+    }
+    return hipGetLastError();
+}
+
+long n_cplx(const Geo &g) { return 4L * g.Vh * 12; }
+
+}  // namespace cstar

@@ -1,0 +1,239 @@
+"""Python binding of libcstar.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels and host solver; this
+module converts numpy / torch arguments to the C ABI of include/cstar.h and
+raises on any non-OK status.  If the library has not been built the import of
+`lib()` fails loudly -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcstar.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cstar.h")
+
+FP64, FP32, FP32_BF16LINKS = 0, 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EAMBIG, ESTATE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "EAMBIG", -6: "ESTATE"}
+
+
+class CstarError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int), ("L", ctypes.c_int), ("time_bc", ctypes.c_int), ("q", ctypes.c_double),
+                ("csw_su3", ctypes.c_double), ("csw_u1", ctypes.c_double)]
+
+
+class EigOpts(ctypes.Structure):
+    _fields_ = [("inner", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("block", ctypes.c_int), ("degree", ctypes.c_int), ("use_nn", ctypes.c_int),
+                ("warm_start", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("applies_fp64", ctypes.c_long), ("applies_inner", ctypes.c_long),
+                ("seconds", ctypes.c_double), ("lambda_max_est", ctypes.c_double)]
+
+
+class SignOpts(ctypes.Structure):
+    _fields_ = [("eig", EigOpts), ("k", ctypes.c_int), ("c", ctypes.c_double), ("m_max", ctypes.c_double)]
+
+
+class SignReport(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int), ("m", ctypes.c_double * 512), ("lambda_bar", ctypes.c_double * 512),
+                ("n_crossings", ctypes.c_int), ("applies", ctypes.c_long), ("seconds", ctypes.c_double)]
+
+
+class ApplyTiming(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_long * 3), ("rhs", ctypes.c_long * 3), ("ms", ctypes.c_double * 3)]
+
+
+PROVIDER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+_lib = None
+
+
+def lib():
+    """Load libcstar.so (built by build.py / __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2108_11989_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        L.cstar_last_error.restype = ctypes.c_char_p
+        L.cstar_gauge_create.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.cstar_gauge_destroy.argtypes = [vp]
+        L.cstar_gauge_destroy.restype = None
+        L.cstar_spinor_bytes.argtypes = [vp, ctypes.c_int]
+        L.cstar_spinor_bytes.restype = ctypes.c_size_t
+        L.cstar_n_sites.argtypes = [vp]
+        L.cstar_n_sites.restype = ctypes.c_long
+        L.cstar_spinor_pack.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.cstar_spinor_unpack.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.dirac_apply.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.q_lowest_eigs.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(EigOpts), dp, dp, vp,
+                                    ctypes.POINTER(EigStats)]
+        L.pfaffian_sign.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(SignOpts), ip, ctypes.POINTER(SignReport)]
+        L.cstar_sign_driver.argtypes = [PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ip, ctypes.POINTER(SignReport)]
+        L.cstar_clover_norm_max.argtypes = [vp, dp]
+        L.cstar_timing_enable.argtypes = [vp, ctypes.c_int]
+        L.cstar_timing_read.argtypes = [vp, ctypes.POINTER(ApplyTiming)]
+        for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
+                     "q_lowest_eigs", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
+                     "cstar_timing_enable", "cstar_timing_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/cstar.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    pat = r"^\s*(?:cstar_status|void|const\s+char\s*\*|size_t|long)\s*\**\s*([A-Za-z_]\w*)\s*\("
+    return re.findall(pat, txt, flags=re.M)
+
+
+def _check(st):
+    if st != OK:
+        raise CstarError(st, lib().cstar_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def eig_opts(inner=FP32_BF16LINKS, tol=1e-10, max_iter=300, block=0, degree=0, use_nn=0, warm_start=0,
+             seed=12345) -> EigOpts:
+    return EigOpts(inner, tol, max_iter, block, degree, use_nn, warm_start, seed)
+
+
+class Gauge:
+    """One gauge field and one quark charge on the device (a cstar_gauge handle)."""
+
+    def __init__(self, su3, theta, q, csw_su3=1.9, csw_u1=1.0, time_bc=1, stream=None):
+        """su3/theta: host numpy arrays, or torch tensors on the device (complex128 / float64,
+        physical-lattice layout of include/cstar.h) -- then no data crosses PCIe."""
+        self.T, self.L = su3.shape[0], su3.shape[1]
+        self.params = Params(self.T, self.L, int(time_bc), float(q), float(csw_su3), float(csw_u1))
+        h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream)
+        if hasattr(su3, "data_ptr"):
+            if not (su3.is_cuda and theta.is_cuda and su3.is_contiguous() and theta.is_contiguous()):
+                raise ValueError("device field tensors must be contiguous CUDA tensors")
+            ps = ctypes.cast(ctypes.c_void_p(su3.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            pt = ctypes.cast(ctypes.c_void_p(theta.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            _check(lib().cstar_gauge_create(ctypes.byref(self.params), ps, pt, 1, s, ctypes.byref(h)))
+        else:
+            su3 = np.ascontiguousarray(su3, dtype=np.complex128)
+            theta = np.ascontiguousarray(theta, dtype=np.float64)
+            _check(lib().cstar_gauge_create(ctypes.byref(self.params), _dp(su3.view(np.float64)), _dp(theta), 0, s,
+                                            ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().cstar_gauge_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_sites(self) -> int:
+        return lib().cstar_n_sites(self.h)
+
+    def spinor_bytes(self, prec=FP64) -> int:
+        return lib().cstar_spinor_bytes(self.h, prec)
+
+    def clover_norm_max(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().cstar_clover_norm_max(self.h, ctypes.byref(v)))
+        return v.value
+
+    def timing(self, on=True):
+        _check(lib().cstar_timing_enable(self.h, int(bool(on))))
+
+    def read_timing(self) -> dict:
+        t = ApplyTiming()
+        _check(lib().cstar_timing_read(self.h, ctypes.byref(t)))
+        return {p: dict(launches=t.launches[p], rhs=t.rhs[p], ms=t.ms[p]) for p in range(3)}
+
+    # --- device buffers are torch tensors; the library reads/writes their memory
+    def new_native(self, nrhs=1, prec=FP64):
+        """Uninitialised native spinor block on the device (torch tensor)."""
+        import torch
+        nbytes = self.spinor_bytes(prec) * nrhs
+        if prec == FP64:
+            return torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+        return torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+
+    def pack(self, canonical, native, prec=FP64, nrhs=1):
+        _check(lib().cstar_spinor_pack(self.h, prec, nrhs, ctypes.c_void_p(canonical.data_ptr()),
+                                       ctypes.c_void_p(native.data_ptr())))
+
+    def unpack(self, native, canonical, prec=FP64, nrhs=1):
+        _check(lib().cstar_spinor_unpack(self.h, prec, nrhs, ctypes.c_void_p(native.data_ptr()),
+                                         ctypes.c_void_p(canonical.data_ptr())))
+
+    def apply(self, native_in, native_out, masses, prec=FP64, gamma5=False):
+        m = np.ascontiguousarray(np.atleast_1d(np.asarray(masses, dtype=np.float64)))
+        _check(lib().dirac_apply(self.h, len(m), _dp(m), prec, int(bool(gamma5)),
+                                 ctypes.c_void_p(native_in.data_ptr()), ctypes.c_void_p(native_out.data_ptr())))
+
+    def lowest_eigs(self, m0, k, opts: EigOpts | None = None, evecs=None, raise_on_noconv=True):
+        ev = np.zeros(k)
+        res = np.zeros(k)
+        st = EigStats()
+        o = opts if opts is not None else eig_opts()
+        ptr = ctypes.c_void_p(evecs.data_ptr()) if evecs is not None else None
+        status = lib().q_lowest_eigs(self.h, float(m0), int(k), ctypes.byref(o), _dp(ev), _dp(res), ptr,
+                                     ctypes.byref(st))
+        if status != OK and (raise_on_noconv or status != ENOCONV):
+            _check(status)
+        return ev, res, st
+
+    def pfaffian_sign(self, m_path, k=4, c=1.9, m_max=0.0, eig: EigOpts | None = None):
+        m = np.ascontiguousarray(np.asarray(m_path, dtype=np.float64))
+        out = np.zeros(len(m), dtype=np.int32)
+        rep = SignReport()
+        o = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), float(m_max))
+        _check(lib().pfaffian_sign(self.h, _dp(m), len(m), ctypes.byref(o),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep)))
+        return out, rep
+
+
+def sign_driver(provider, m_path, k, c, m_max):
+    """Run the library's sign driver over a Python eigenvalue provider(m, k) -> (evals, errs)."""
+    def cb(ctx, m, kk, ev, er):
+        try:
+            e, r = provider(m, kk)
+            for i in range(kk):
+                ev[i] = float(e[i])
+                er[i] = float(r[i])
+            return 0
+        except Exception:
+            return 1
+
+    cbf = PROVIDER(cb)
+    m = np.ascontiguousarray(np.asarray(m_path, dtype=np.float64))
+    out = np.zeros(len(m), dtype=np.int32)
+    rep = SignReport()
+    st = lib().cstar_sign_driver(cbf, None, _dp(m), len(m), int(k), float(c), float(m_max),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep))
+    return st, out, rep

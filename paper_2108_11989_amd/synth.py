@@ -98,10 +98,59 @@ def ape_smooth(su3: np.ndarray, theta: np.ndarray, steps: int, alpha: float = 0.
     return u, th
 
 
-def make_field(T: int, L: int, eps: float, seed: int, smear_steps: int = 0, alpha: float = 0.5):
+def ape_smooth_torch(su3: np.ndarray, theta: np.ndarray, steps: int, alpha: float = 0.5, device=None):
+    """The same smoothing rule as ape_smooth, evaluated with torch (on the GPU
+    when one is present): only a faster way to shape large synthetic inputs."""
+    import torch
+    dev = device or ("cuda" if torch.cuda.is_available() else "cpu")
+    u = torch.from_numpy(su3).to(dev)
+    th = torch.from_numpy(theta).to(dev)
+
+    def roll(a, mu, step):
+        return torch.roll(a, -step, dims=mu)
+
+    def dag(a):
+        return a.conj().transpose(-1, -2)
+
+    def reunit(m):
+        r0 = m[..., 0, :]
+        r0 = r0 / torch.linalg.vector_norm(r0, dim=-1, keepdim=True)
+        r1 = m[..., 1, :]
+        r1 = r1 - torch.sum(r0.conj() * r1, dim=-1, keepdim=True) * r0
+        r1 = r1 / torch.linalg.vector_norm(r1, dim=-1, keepdim=True)
+        r2 = torch.stack([r0[..., 1] * r1[..., 2] - r0[..., 2] * r1[..., 1],
+                          r0[..., 2] * r1[..., 0] - r0[..., 0] * r1[..., 2],
+                          r0[..., 0] * r1[..., 1] - r0[..., 1] * r1[..., 0]], dim=-1).conj()
+        return torch.stack([r0, r1, r2], dim=-2)
+
+    for _ in range(steps):
+        new_u = torch.empty_like(u)
+        new_th = torch.empty_like(th)
+        for mu in range(4):
+            stap = torch.zeros_like(u[..., mu, :, :])
+            zst = torch.zeros(th.shape[:4], dtype=torch.complex128, device=dev)
+            for nu in range(4):
+                if nu == mu:
+                    continue
+                u_nu = u[..., nu, :, :]
+                stap = stap + u_nu @ roll(u[..., mu, :, :], nu, 1) @ dag(roll(u[..., nu, :, :], mu, 1))
+                u_nu_m = roll(u[..., nu, :, :], nu, -1)
+                stap = stap + dag(u_nu_m) @ roll(u[..., mu, :, :], nu, -1) @ roll(u_nu_m, mu, 1)
+                zst = zst + torch.exp(1j * (th[..., nu] + roll(th[..., mu], nu, 1) - roll(th[..., nu], mu, 1)))
+                zst = zst + torch.exp(1j * (-roll(th[..., nu], nu, -1) + roll(th[..., mu], nu, -1)
+                                            + roll(roll(th[..., nu], nu, -1), mu, 1)))
+            new_u[..., mu, :, :] = reunit((1 - alpha) * u[..., mu, :, :] + (alpha / 6.0) * stap)
+            new_th[..., mu] = torch.angle((1 - alpha) * torch.exp(1j * th[..., mu]) + (alpha / 6.0) * zst)
+        u, th = new_u, new_th
+    return np.ascontiguousarray(u.cpu().numpy()), np.ascontiguousarray(th.cpu().numpy())
+
+
+def make_field(T: int, L: int, eps: float, seed: int, smear_steps: int = 0, alpha: float = 0.5,
+               smear_backend: str = "numpy"):
     """Random SU(3) x U(1) field on the physical T x L^3 lattice.
 
     Returns (su3 complex128 [T,L,L,L,4,3,3], theta float64 [T,L,L,L,4]).
+    smear_backend "torch" evaluates the smoothing with torch (GPU if present).
     """
     if T < 2 or L < 2 or T % 2 or L % 2:
         raise ValueError("T and L must be even and >= 2")
@@ -112,7 +161,10 @@ def make_field(T: int, L: int, eps: float, seed: int, smear_steps: int = 0, alph
     su3 = su3_from_algebra(r, eps).reshape(T, L, L, L, 4, 3, 3)
     theta = theta.reshape(T, L, L, L, 4)
     if smear_steps:
-        su3, theta = ape_smooth(su3, theta, smear_steps, alpha)
+        if smear_backend == "torch":
+            su3, theta = ape_smooth_torch(su3, theta, smear_steps, alpha)
+        else:
+            su3, theta = ape_smooth(su3, theta, smear_steps, alpha)
     return np.ascontiguousarray(su3), np.ascontiguousarray(theta)
 
 

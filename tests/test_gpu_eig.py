@@ -1,0 +1,88 @@
+"""GPU parity of q_lowest_eigs and pfaffian_sign against the oracle.
+
+Eigenvalues: the k smallest |lambda| of Q = g5 D, one per Kramers pair, must
+agree with the dense oracle spectrum to 1e-10 relative (FP64 and mixed
+precision after FP64 refinement).  Signs: bit-identical to the oracle's dense
+inertia (and, on the small fields, its Pfaffian).
+"""
+import numpy as np
+import pytest
+
+from oracle import dense, sign as osign
+from oracle import dirac as odirac
+from paper_2108_11989_amd import cstar, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _tiny():
+    w = synth.WORKLOADS["tiny_4x2^3"]
+    su3, th = synth.make_field(w["T"], w["L"], w["eps"], w["seed"])
+    return w, su3, th, w["q"][0]
+
+
+@pytest.mark.parametrize("inner", [cstar.FP64, cstar.FP32_BF16LINKS])
+def test_lowest_eigs_tiny_all_kappas(inner):
+    assert torch.cuda.is_available()
+    w, su3, th, q = _tiny()
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    for kappa in w["kappas"]:
+        m0 = float(synth.kappa_to_m0(kappa))
+        print(f"eig tiny kappa={kappa:.4f} inner={inner}", flush=True)
+        lam = osign.pair_spectrum(op, m0)
+        ref = dense.lowest_abs(lam, 4)
+        ev, res, st = g.lowest_eigs(m0, 4, cstar.eig_opts(inner=inner, tol=1e-12, max_iter=400))
+        assert np.all(np.abs(ev - ref) <= 1e-10 * np.abs(ref)), (kappa, ev, ref)
+        # reported residuals bound the true error, up to the dense oracle's own
+        # rounding (LAPACK eigh: a small multiple of eps * ||Q||, ||Q|| < 20 here)
+        assert np.all(np.abs(ev - ref) <= res + 64 * 2.2e-16 * 20)
+    g.close()
+
+
+def test_lowest_eigs_returns_eigenvectors():
+    w, su3, th, q = _tiny()
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    m0 = float(synth.kappa_to_m0(0.11))
+    k = 3
+    vec = g.new_native(k, cstar.FP64)
+    ev, res, st = g.lowest_eigs(m0, k, cstar.eig_opts(inner=cstar.FP64, tol=1e-12), evecs=vec)
+    canon = torch.empty((k,) + op.shape, dtype=torch.complex128, device="cuda")
+    g.unpack(vec, canon, cstar.FP64, k)
+    torch.cuda.synchronize()
+    V = canon.cpu().numpy()
+    for i in range(k):
+        v = V[i] / np.linalg.norm(V[i])
+        r = np.linalg.norm(op.Q(v, m0) - ev[i] * v)
+        assert r <= res[i] * 1.01 + 1e-13
+    g.close()
+
+
+def test_pfaffian_sign_tiny_path_matches_dense_inertia():
+    w, su3, th, q = _tiny()
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    path = synth.kappa_to_m0(w["kappas"])
+    signs, rep = g.pfaffian_sign(path, k=4, eig=cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=1e-10))
+    ref = [osign.sign_inertia(op, m) for m in path]
+    assert list(signs) == ref
+    g.close()
+
+
+@pytest.mark.parametrize("seed,eps", [(13, 1.2), (21, 1.0), (5, 1.4)])
+def test_pfaffian_sign_rough_fields_with_negative_signs(seed, eps):
+    """Rough fields whose flow crosses zero: GPU signs equal inertia and the Pfaffian."""
+    T, L = 4, 2
+    su3, th = synth.make_field(T, L, eps, seed)
+    q = 2 / 3
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    path = np.linspace(-2.0, 0.4, 13)
+    signs, rep = g.pfaffian_sign(path, k=6, eig=cstar.eig_opts(inner=cstar.FP64, tol=1e-10))
+    ref = np.array([osign.sign_inertia(op, m) for m in path])
+    refp = np.array([osign.sign_pfaffian(op, m) for m in path])
+    assert np.array_equal(ref, refp)
+    assert np.array_equal(signs, ref), (signs, ref)
+    g.close()

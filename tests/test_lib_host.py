@@ -1,0 +1,98 @@
+"""Host-side checks of libcstar.so that need no GPU: the library loads, exports
+every function include/cstar.h declares, and its sign driver (host logic of
+pfaffian_sign) gets the sign right on eigenvalue flows known in closed form.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2108_11989_amd import cstar
+
+
+def test_library_exports_every_declared_function():
+    L = cstar.lib()
+    names = cstar.header_functions()
+    for must in ("dirac_apply", "q_lowest_eigs", "pfaffian_sign", "cstar_gauge_create", "cstar_sign_driver"):
+        assert must in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_create_rejects_bad_lattice_without_gpu():
+    su3 = np.zeros((3, 2, 2, 2, 4, 3, 3), dtype=np.complex128)
+    th = np.zeros((3, 2, 2, 2, 4))
+    with pytest.raises(cstar.CstarError) as e:
+        cstar.Gauge(su3, th, 2 / 3)
+    assert e.value.status == cstar.EINVAL
+    su3 = np.zeros((4, 2, 2, 2, 4, 3, 3), dtype=np.complex128)
+    su3[..., 0, 0] = np.nan
+    th = np.zeros((4, 2, 2, 2, 4))
+    with pytest.raises(cstar.CstarError) as e:
+        cstar.Gauge(su3, th, 2 / 3)
+    assert e.value.status == cstar.EINVAL
+
+
+def _flow(seed, n=24):
+    """Eigenvalue flows lambda_i(m) = a_i + s_i m, |s_i| <= 1 (the Feynman-Hellmann bound).
+
+    Crossings m_i* = -a_i/s_i lie inside [-1, 2]; above m = 3 the count of
+    negative values is even, as for Q at large mass.
+    """
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0.2, 1.0, n) * rng.choice([-1, 1], n)
+    mstar = rng.uniform(-1.0, 2.0, n)
+    a = -s * mstar
+    # at m = 3 every lambda has the sign of s; make the negative count even
+    if np.sum(s < 0) % 2:
+        s[0] = -s[0]
+        a[0] = -s[0] * mstar[0]
+    return a, s
+
+
+def _provider(a, s, err=1e-12):
+    def prov(m, k):
+        lam = a + s * m
+        order = np.lexsort((lam, np.abs(lam)))[:k]
+        return lam[order], np.full(k, err)
+    return prov
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_sign_driver_on_closed_form_flows(seed):
+    a, s = _flow(seed)
+    path = np.linspace(-0.9, 2.5, 9)
+    st, signs, rep = cstar.sign_driver(_provider(a, s), path, k=6, c=1.9, m_max=3.0)
+    assert st == cstar.OK, cstar.lib().cstar_last_error()
+    n_top = np.sum(a + s * 3.0 < 0)
+    for m, sg in zip(path, signs):
+        n = np.sum(a + s * m < 0)
+        assert sg == (-1 if (n - n_top) % 2 else 1), (m, n, n_top)
+    assert rep.n_points >= len(path)
+
+
+def test_sign_driver_step_a_without_crossings():
+    # one flow rising from the target: step A reaches m_max without a decrease
+    a = np.array([0.05, 0.3, 0.9, 1.4])
+    s = np.array([0.9, 0.7, 0.5, 0.5])
+    st, signs, rep = cstar.sign_driver(_provider(a, s), [0.0], k=4, c=1.9, m_max=4.0)
+    assert st == cstar.OK and signs[0] == 1
+    ms = np.array(rep.m[: rep.n_points])
+    lb = np.array(rep.lambda_bar[: rep.n_points])
+    # the solved masses after the target follow m_{n+1} = m_n + c * lambda_bar_n
+    # until they overshoot the top point
+    assert np.isclose(ms[0], 0.0)
+    assert rep.n_points < 12
+
+
+def test_sign_driver_ambiguous_path_point():
+    a = np.array([0.0, 0.5])
+    s = np.array([1.0, 1.0])
+    st, signs, rep = cstar.sign_driver(_provider(a, s, err=1e-9), [0.0, 1.0], k=2, c=1.9, m_max=2.0)
+    assert st == cstar.EAMBIG
+    assert signs[0] == 0
+
+
+def test_sign_driver_rejects_bad_c():
+    st, _, _ = cstar.sign_driver(_provider(np.ones(2), np.ones(2)), [0.0], k=2, c=2.5, m_max=1.0)
+    assert st == cstar.EINVAL
