@@ -67,6 +67,48 @@ def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
             "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3 (clover setup {t_setup:.1f} s not counted)"}
 
 
+def kernel_probe(args, su3_d, th_d, q, T, L):
+    """Time the apply kernels alone (single RHS in every precision, and the
+    solver's multi-RHS block in the inner precision) with HIP events."""
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+    nsites2 = 2 * T * L ** 3
+    nb = args.probe_nrhs or (2 * args.k + max(12, args.k))
+    res = {}
+    for prec, name in [(cstar.FP64, "fp64"), (cstar.FP32, "fp32"), (cstar.FP32_BF16LINKS, "bf16")]:
+        for nrhs in (1, nb):
+            nin, nout = g.new_native(nrhs, prec), g.new_native(nrhs, prec)
+            nin.normal_()
+            masses = [-0.3] * nrhs
+            for _ in range(2):
+                g.apply(nin, nout, masses, prec, True)
+            g.timing(True)
+            for _ in range(args.probe_reps):
+                g.apply(nin, nout, masses, prec, True)
+            tm = g.read_timing()[prec]
+            g.timing(False)
+            avg = tm["ms"] / tm["launches"]
+            gbs = algorithmic_bytes(prec, nsites2, tm["launches"], tm["rhs"]) / (tm["ms"] * 1e-3) / 1e9
+            res[f"{name}_x{nrhs}"] = {"avg_ms": avg, "GBs": gbs, "applies_per_s": nrhs / (avg * 1e-3)}
+            log(f"[probe] {name} nrhs={nrhs}: {avg:.4f} ms/launch, {nrhs / (avg * 1e-3):.0f} applies/s, "
+                f"{gbs:.0f} GB/s algorithmic ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+            del nin, nout
+    if args.copy_probe_gib > 0:
+        n = int(args.copy_probe_gib * (1 << 30) // 4)
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # blit copy
+        torch.mul(a, 1.0, out=b)  # elementwise kernel: 16-byte vector loads per lane, like the apply kernels
+        torch.cuda.synchronize()
+        log(f"[probe] device copy (blit and elementwise) of {n * 4} bytes done")
+    g.close()
+    print(json.dumps({"kernel_probe": res, "lattice": f"{T}x{L}^3"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +120,12 @@ def main():
     ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--path-points", type=int, default=0, help="use only the first n kappas (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only time the apply kernels on the workload lattice (for profiler runs)")
+    ap.add_argument("--probe-reps", type=int, default=20)
+    ap.add_argument("--probe-nrhs", type=int, default=0, help="multi-RHS width of the probe (0: the solver block)")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run one device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -102,6 +150,9 @@ def main():
     log(f"[bench] field generated in {time.time() - t0:.1f} s")
     su3_d = torch.from_numpy(su3).cuda().contiguous()
     th_d = torch.from_numpy(th).cuda().contiguous()
+    if args.kernel_probe:
+        kernel_probe(args, su3_d, th_d, q, T, L)
+        return
     kappas = w["kappas"] if args.path_points <= 0 else w["kappas"][: args.path_points]
     masses = np.asarray(synth.kappa_to_m0(kappas), dtype=np.float64)
     inner = {"bf16": cstar.FP32_BF16LINKS, "fp32": cstar.FP32, "fp64": cstar.FP64}[args.inner]

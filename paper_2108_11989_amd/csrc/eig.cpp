@@ -98,14 +98,26 @@ struct Ctx {
     long ap64 = 0, ap_inner = 0;
 };
 
-// out = Q in on nv FP64 vectors
-hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv) {
+// out = ea * Q in [+ eb * y + ec * z] on nv FP64 vectors
+hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv, double ea = 1.0, const double2 *y = nullptr,
+               double eb = 0.0, const double2 *z = nullptr, double ec = 0.0) {
     ApplyArgs a{in, out, (long)c.w->n * (long)sizeof(double2), nv, 1, nullptr, c.m};
+    a.y = y;
+    a.z = z;
+    a.ea = ea;
+    a.eb = eb;
+    a.ec = ec;
     c.ap64 += nv;
     return handle_apply(c.g, CSTAR_FP64, a);
 }
-hipError_t q32(Ctx &c, cstar_prec prec, const float4 *in, float4 *out, int nv) {
+hipError_t q32(Ctx &c, cstar_prec prec, const float4 *in, float4 *out, int nv, double ea = 1.0,
+               const float4 *y = nullptr, double eb = 0.0, const float4 *z = nullptr, double ec = 0.0) {
     ApplyArgs a{in, out, (long)c.w->n / 2 * (long)sizeof(float4), nv, 1, nullptr, c.m};
+    a.y = y;
+    a.z = z;
+    a.ea = ea;
+    a.eb = eb;
+    a.ec = ec;
     c.ap_inner += nv;
     return handle_apply(c.g, prec, a);
 }
@@ -128,12 +140,13 @@ cstar_status gram(Ctx &c, const double2 *V, int nv, const double2 *W, int nw, st
     return CSTAR_OK;
 }
 
-// O = V C with C (nv x no) host row-major
-cstar_status combine(Ctx &c, const double2 *V, int nv, const std::vector<zd> &C, int no, double2 *O) {
+// O = beta O + V C with C (nv x no) host row-major
+cstar_status combine(Ctx &c, const double2 *V, int nv, const std::vector<zd> &C, int no, double2 *O,
+                     double beta = 0.0) {
     std::vector<double2> h((size_t)nv * no);
     for (size_t i = 0; i < h.size(); i++) h[i] = make_double2(C[i].real(), C[i].imag());
     CSTAR_HIP(hipMemcpyAsync(c.w->C, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, c.s));
-    CSTAR_HIP(launch_combine(V, c.w->n, nv, c.w->C, no, O, c.w->n, no, c.w->n, c.s));
+    CSTAR_HIP(launch_combine(V, c.w->n, nv, c.w->C, no, O, c.w->n, no, c.w->n, c.s, beta));
     CSTAR_HIP(hipStreamSynchronize(c.s));  // C staging buffer is reused by the next call
     return CSTAR_OK;
 }
@@ -169,14 +182,12 @@ cstar_status orthonormalise(Ctx &c, double2 *Y, int nv, double2 *tmp, int *kept)
 }
 
 // Y <- Y - X (X^H Y)
-cstar_status project_out(Ctx &c, const double2 *X, int nx, double2 *Y, int ny, double2 *tmp) {
+cstar_status project_out(Ctx &c, const double2 *X, int nx, double2 *Y, int ny) {
     std::vector<zd> G;
     cstar_status st = gram(c, X, nx, Y, ny, G);
     if (st) return st;
-    st = combine(c, X, nx, G, ny, tmp);
-    if (st) return st;
-    CSTAR_HIP(launch_lincomb64(2L * c.w->n * ny, -1.0, (const double *)tmp, 1.0, (double *)Y, 0.0, nullptr, c.s));
-    return CSTAR_OK;
+    for (auto &v : G) v = -v;
+    return combine(c, X, nx, G, ny, Y, 1.0);
 }
 
 // Rayleigh-Ritz of H = V^H A V in the basis V (nt vectors) with its overlap
@@ -221,32 +232,29 @@ void rr_generalised(int nt, const std::vector<zd> &H, const std::vector<zd> &M, 
     *rank = r;
 }
 
-// Chebyshev filter Y = T_d(x(A)) X / T_d(x(a0)), x(t) = (t - cen)/e, in FP64.
+// Chebyshev filter Y = T_d(x(A)) X / T_d(x(a0)), x(t) = (t - cen)/e, A = Q^2.
 // Three-term recurrence with the normalisation sigma_j = T_{j-1}(x0)/T_j(x0):
 //   Y_1 = sigma_1/e (A - cen) X,  Y_{j+1} = 2 sigma_{j+1}/e (A - cen) Y_j - sigma_j sigma_{j+1} Y_{j-1},
 //   sigma_1 = 1/x0, sigma_{j+1} = 1/(2 x0 - sigma_j).
-// Buffers: three rotating blocks (Yout, B1, B2) and one for Q * Y_j (BQ); X is read only.
+// Each step is two Q applies; the second forms the three-term update in its
+// epilogue.  FP64 buffers: three rotating blocks (Yout, B1, B2) and BQ for
+// Q Y_j; X is read only.
 cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0, double acut, double bup, int deg,
                       double2 *B1, double2 *B2, double2 *BQ) {
     const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
     const double x0 = (a0 - cen) / e;
     double sig = 1.0 / x0;
-    const long nr = 2L * c.w->n * nv;
     double2 *buf[3] = {Yout, B1, B2};
     int icur = 0, iprev = -1;  // iprev = -1 means X
     CSTAR_HIP(q64(c, X, BQ, nv));
-    CSTAR_HIP(q64(c, BQ, buf[icur], nv));
-    CSTAR_HIP(launch_lincomb64(nr, -cen * sig / e, (const double *)X, sig / e, (double *)buf[icur], 0.0, nullptr,
-                               c.s));
+    CSTAR_HIP(q64(c, BQ, buf[icur], nv, sig / e, X, -cen * sig / e));
     for (int j = 1; j < deg; j++) {
         const double sig2 = 1.0 / (2.0 * x0 - sig);
         int inext = 0;
         while (inext == icur || inext == iprev) inext++;
         const double2 *prev = iprev < 0 ? X : buf[iprev];
         CSTAR_HIP(q64(c, buf[icur], BQ, nv));
-        CSTAR_HIP(q64(c, BQ, buf[inext], nv));
-        CSTAR_HIP(launch_lincomb64(nr, -2.0 * sig2 * cen / e, (const double *)buf[icur], 2.0 * sig2 / e,
-                                   (double *)buf[inext], -sig * sig2, (const double *)prev, c.s));
+        CSTAR_HIP(q64(c, BQ, buf[inext], nv, 2.0 * sig2 / e, buf[icur], -2.0 * sig2 * cen / e, prev, -sig * sig2));
         iprev = icur;
         icur = inext;
         sig = sig2;
@@ -256,26 +264,22 @@ cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0
     return CSTAR_OK;
 }
 
-// The same filter in FP32 on the F[] buffers: F[0] = X (converted), result converted to Yout.
+// The same filter in an FP32 form on the F[] buffers: F[0] = X (converted),
+// the result converted back into Yout.
 cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2 *Yout, double a0, double acut,
                       double bup, int deg) {
     Workspace *w = c.w;
     const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
     const double x0 = (a0 - cen) / e;
     double sig = 1.0 / x0;
-    const long nr = 2L * w->n * nv;  // reals
     float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
     CSTAR_HIP(launch_to_f32(c.g->geo, nv, X, prev, c.s));
     CSTAR_HIP(q32(c, prec, prev, tq, nv));
-    CSTAR_HIP(q32(c, prec, tq, cur, nv));
-    CSTAR_HIP(launch_lincomb32(nr, (float)(-cen * sig / e), (const float *)prev, (float)(sig / e), (float *)cur, 0.f,
-                               nullptr, c.s));
+    CSTAR_HIP(q32(c, prec, tq, cur, nv, sig / e, prev, -cen * sig / e));
     for (int j = 1; j < deg; j++) {
         const double sig2 = 1.0 / (2.0 * x0 - sig);
         CSTAR_HIP(q32(c, prec, cur, tq, nv));
-        CSTAR_HIP(q32(c, prec, tq, nxt, nv));
-        CSTAR_HIP(launch_lincomb32(nr, (float)(-2.0 * sig2 * cen / e), (const float *)cur, (float)(2.0 * sig2 / e),
-                                   (float *)nxt, (float)(-sig * sig2), (const float *)prev, c.s));
+        CSTAR_HIP(q32(c, prec, tq, nxt, nv, 2.0 * sig2 / e, cur, -2.0 * sig2 * cen / e, prev, -sig * sig2));
         float4 *t = prev;
         prev = cur;
         cur = nxt;
@@ -298,7 +302,9 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     if (opts_in) o = *opts_in;
     if (k < 1 || k > 30) return fail(CSTAR_EINVAL, "q_lowest_eigs: k must be in [1, 30]");
     if (!(o.tol > 0) || o.max_iter < 1) return fail(CSTAR_EINVAL, "q_lowest_eigs: bad tol/max_iter");
-    int nb = o.block > 0 ? o.block : 2 * k + std::max(4, k / 2);
+    // guard vectors: the low spectrum of smooth fields comes in near-degenerate
+    // multiplets; the block must hold a whole multiplet beyond the wanted ones
+    int nb = o.block > 0 ? o.block : 2 * k + std::max(12, k);
     nb = std::max(nb, 2 * k);
     if (nb > 64) return fail(CSTAR_EINVAL, "q_lowest_eigs: block must be <= 64");
     int deg = o.degree > 0 ? o.degree : 24;
@@ -334,52 +340,73 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     const char *venv = getenv("CSTAR_VERBOSE");
     const bool verbose = venv && venv[0] == '1';
     bool fp64_filter = (inner == CSTAR_FP64);
-    double last_rmax = 1e300, last_rabs = 1e300;
+    double last_rabs = 1e300;
     int stall = 0;
+    int nq = nb;  // size of the Q-reduced leading subspace (set after each RR)
     std::vector<double> lam_out(k), res_out(k);
     bool converged = false;
     int it = 0;
-    // signed Ritz data of the last iteration
     for (it = 0; it < o.max_iter; it++) {
-        int ny = nb;
+        int ny = 0;
         if (have_ritz) {
-            // ---- filter
+            // ---- filter: the whole block in the inner precisions; in FP64 only
+            // the leading nq vectors (the guard vectors beyond the Q-reduced
+            // subspace need no FP64 accuracy)
+            const int nf = fp64_filter ? nq : nb;
             if (hooks && hooks->precondition && o.use_nn) {
-                st = hooks->precondition(hooks->ctx, g, m0, X, nb, Y);
+                st = hooks->precondition(hooks->ctx, g, m0, X, nf, Y);
                 if (st) return st;
             } else if (fp64_filter) {
-                st = filter64(c, X, nb, Y, a0, acut, bup, deg, w->T, w->T2, AY);
+                st = filter64(c, X, nf, Y, a0, acut, bup, deg, w->T, w->T2, AY);
             } else {
-                st = filter32(c, inner, X, nb, Y, a0, acut, bup, deg);
+                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg);
             }
             if (st) return st;
-            // ---- orthogonalise against X twice, then within
+            // ---- orthogonalise against X twice, then orthonormalise within
             for (int r = 0; r < 2; r++) {
-                st = project_out(c, X, nb, Y, nb, w->T);
+                st = project_out(c, X, nb, Y, nf);
                 if (st) return st;
             }
-            st = orthonormalise(c, Y, nb, w->T, &ny);
+            st = orthonormalise(c, Y, nf, w->T, &ny);
             if (st) return st;
-            if (ny > 0) {
-                st = project_out(c, X, nb, Y, ny, w->T);
-                if (st) return st;
-                st = orthonormalise(c, Y, ny, w->T, &ny);
-                if (st) return st;
-            }
             if (ny > 0) {
                 CSTAR_HIP(q64(c, Y, w->T, ny));
                 CSTAR_HIP(q64(c, w->T, AY, ny));
             }
-        } else {
-            ny = 0;
         }
-        // ---- Rayleigh-Ritz with A on [X Y] (generalised: overlap computed, not assumed)
+        // ---- Rayleigh-Ritz with A on [X Y], generalised (overlap computed).
+        // After the first iteration X is the previous M-orthonormal Ritz block:
+        // X^H A X = diag(theta) and X^H X = 1 are known; the Y columns are
+        // formed with one pass over [X Y] for each of A Y and Y.
         const int nt = nb + ny;
-        std::vector<zd> H, Mo;
-        st = gram(c, w->XY, nt, w->AXY, nt, H);
-        if (st) return st;
-        st = gram(c, w->XY, nt, w->XY, nt, Mo);
-        if (st) return st;
+        std::vector<zd> H((size_t)nt * nt, zd(0, 0)), Mo((size_t)nt * nt, zd(0, 0));
+        if (!have_ritz) {
+            st = gram(c, X, nb, AX, nb, H);
+            if (st) return st;
+            st = gram(c, X, nb, X, nb, Mo);
+            if (st) return st;
+        } else {
+            for (int i = 0; i < nb; i++) {
+                H[(size_t)i * nt + i] = theta[i];
+                Mo[(size_t)i * nt + i] = 1.0;
+            }
+            if (ny > 0) {
+                std::vector<zd> GA, GM;
+                st = gram(c, w->XY, nt, AY, ny, GA);
+                if (st) return st;
+                st = gram(c, w->XY, nt, Y, ny, GM);
+                if (st) return st;
+                for (int i = 0; i < nt; i++)
+                    for (int j = 0; j < ny; j++) {
+                        H[(size_t)i * nt + nb + j] = GA[(size_t)i * ny + j];
+                        Mo[(size_t)i * nt + nb + j] = GM[(size_t)i * ny + j];
+                        if (i < nb) {
+                            H[(size_t)(nb + j) * nt + i] = std::conj(GA[(size_t)i * ny + j]);
+                            Mo[(size_t)(nb + j) * nt + i] = std::conj(GM[(size_t)i * ny + j]);
+                        }
+                    }
+            }
+        }
         std::vector<double> th;
         std::vector<zd> S;
         int rank = 0;
@@ -400,42 +427,57 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
         if (acut >= bup) acut = 0.5 * bup;
         have_ritz = true;
 
-        // ---- signed Rayleigh-Ritz with Q on X: QX in the Y slot
-        CSTAR_HIP(q64(c, X, Y, nb));
-        std::vector<zd> HQ, MX;
-        st = gram(c, X, nb, Y, nb, HQ);
+        // ---- signed Rayleigh-Ritz with Q on the leading nq Ritz vectors of A.
+        // An eigenspace of A = Q^2 holds both +lambda and -lambda when both
+        // occur (near-free fields have such multiplets); Q is reduced only on a
+        // complete one, so the subspace ends at the largest relative gap of the
+        // A-Ritz values at or beyond the 2k wanted ones.  QX in the Y slot.
+        nq = nb;
+        {
+            double best = -1.0;
+            for (int j = 2 * k; j < nb; j++) {
+                const double gap = (theta[j] - theta[j - 1]) / std::max(theta[j], 1e-300);
+                if (gap > best) {
+                    best = gap;
+                    nq = j;
+                }
+            }
+        }
+        CSTAR_HIP(q64(c, X, Y, nq));
+        std::vector<zd> HQ;
+        st = gram(c, X, nq, Y, nq, HQ);
         if (st) return st;
-        st = gram(c, X, nb, X, nb, MX);
-        if (st) return st;
+        std::vector<zd> MX((size_t)nq * nq, zd(0, 0));
+        for (int i = 0; i < nq; i++) MX[(size_t)i * nq + i] = 1.0;
         std::vector<double> lq;
         std::vector<zd> SQfull;
         int rq = 0;
-        rr_generalised(nb, HQ, MX, lq, SQfull, &rq);
-        if (rq < nb) return fail(CSTAR_EDEVICE, "q_lowest_eigs: Ritz block lost rank");
+        rr_generalised(nq, HQ, MX, lq, SQfull, &rq);
+        if (rq < nq) return fail(CSTAR_EDEVICE, "q_lowest_eigs: Ritz block lost rank");
         std::vector<zd> &SQ = SQfull;
-        // R = Q X S - X S diag(lq) = [X, QX] [-S L; S]
-        std::vector<zd> RC((size_t)2 * nb * nb);
-        for (int i = 0; i < nb; i++)
-            for (int j = 0; j < nb; j++) {
-                RC[(size_t)i * nb + j] = -SQ[(size_t)i * nb + j] * lq[j];
-                RC[(size_t)(nb + i) * nb + j] = SQ[(size_t)i * nb + j];
+        // R = Q X S - X S diag(lq) = [X, QX] [-S L; S]  (QX at column nb of XY)
+        std::vector<zd> RC((size_t)(nb + nq) * nq, zd(0, 0));
+        for (int i = 0; i < nq; i++)
+            for (int j = 0; j < nq; j++) {
+                RC[(size_t)i * nq + j] = -SQ[(size_t)i * nq + j] * lq[j];
+                RC[(size_t)(nb + i) * nq + j] = SQ[(size_t)i * nq + j];
             }
-        st = combine(c, w->XY, 2 * nb, RC, nb, w->T);
+        st = combine(c, w->XY, nb + nq, RC, nq, w->T);
         if (st) return st;
         std::vector<zd> RR;
-        st = gram(c, w->T, nb, w->T, nb, RR);
+        st = gram(c, w->T, nq, w->T, nq, RR);
         if (st) return st;
-        std::vector<double> rn(nb);
-        for (int j = 0; j < nb; j++) rn[j] = std::sqrt(std::max(0.0, RR[(size_t)j * nb + j].real()));
+        std::vector<double> rn(nq);
+        for (int j = 0; j < nq; j++) rn[j] = std::sqrt(std::max(0.0, RR[(size_t)j * nq + j].real()));
         // Kramers pairing: walk the signed Ritz values upwards and pair neighbours
         // that agree within their residuals; then order pairs by |lambda|.
-        std::vector<int> ord(nb);
-        for (int j = 0; j < nb; j++) ord[j] = j;
+        std::vector<int> ord(nq);
+        for (int j = 0; j < nq; j++) ord[j] = j;
         std::sort(ord.begin(), ord.end(), [&](int a, int b) { return lq[a] < lq[b]; });
         struct Pr { double lam, err; int a; };
         std::vector<Pr> prs;
         const double qscale = std::sqrt(bup);
-        for (int i = 0; i + 1 < nb;) {
+        for (int i = 0; i + 1 < nq;) {
             const int a = ord[i], b = ord[i + 1];
             const double gap = std::fabs(lq[a] - lq[b]);
             if (gap <= 2.0 * (rn[a] + rn[b]) + 1e-13 * qscale) {
@@ -462,50 +504,59 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             rmax = std::max(rmax, res_out[i] / std::max(std::fabs(lam_out[i]), 1e-3));
         }
         if (verbose)
-            fprintf(stderr, "[cstar eig] m=%.6f it=%d nb=%d ny=%d deg=%d pairs=%zu fp64filter=%d acut=%.3e rmax=%.3e lam0=%.6e res0=%.2e\n",
-                    m0, it, nb, ny, deg, prs.size(), (int)fp64_filter, acut, rmax, prs.empty() ? 0.0 : prs[0].lam,
+            fprintf(stderr, "[cstar eig] m=%.6f it=%d nb=%d nq=%d ny=%d deg=%d pairs=%zu filter=%s acut=%.3e rmax=%.3e lam0=%.6e res0=%.2e\n",
+                    m0, it, nb, nq, ny, deg, prs.size(), fp64_filter ? "fp64" : (inner == CSTAR_FP32 ? "fp32" : "bf16"), acut, rmax, prs.empty() ? 0.0 : prs[0].lam,
                     prs.empty() ? 0.0 : prs[0].err);
         // a wanted pair must also be separated from the unpaired / guard Ritz values
         if (ok) {
             converged = true;
             if (evecs) {
-                std::vector<zd> Sv((size_t)nb * k);
-                for (int i = 0; i < nb; i++)
-                    for (int j = 0; j < k; j++) Sv[(size_t)i * k + j] = SQ[(size_t)i * nb + prs[j].a];
-                st = combine(c, X, nb, Sv, k, (double2 *)evecs);
+                std::vector<zd> Sv((size_t)nq * k);
+                for (int i = 0; i < nq; i++)
+                    for (int j = 0; j < k; j++) Sv[(size_t)i * k + j] = SQ[(size_t)i * nq + prs[j].a];
+                st = combine(c, X, nq, Sv, k, (double2 *)evecs);
                 if (st) return st;
             }
             w->warm_nb = nb;
             it++;
             break;
         }
-        // precision switch: the inner filter generates search directions until the
-        // wanted residuals reach its noise floor (the inner operator differs from
-        // the FP64 one by ~2^-8 relative for BF16 links, ~2^-23 for FP32), or stop
-        // improving for three iterations; then the filter runs in FP64.
+        // precision ladder: the filter runs in BF16-link, then FP32-link, then
+        // FP64 arithmetic; each level generates search directions until the
+        // wanted residuals reach its noise floor (the level's operator differs
+        // from the FP64 one by ~2^-8 relative for BF16 links, ~2^-23 for FP32),
+        // or stop improving for three iterations.
         double rabs = 0.0;
         for (int i = 0; i < k && i < (int)prs.size(); i++) rabs = std::max(rabs, prs[i].err);
         if ((int)prs.size() < k) rabs = 1e300;
-        const double floor_inner = (inner == CSTAR_FP32_BF16LINKS ? 4e-3 : 1e-6) * qscale;
         stall = (rabs > 0.8 * last_rabs) ? stall + 1 : 0;
-        if (!fp64_filter && (rabs < 20.0 * floor_inner || stall >= 3)) {
-            fp64_filter = true;
-            stall = 0;
+        if (!fp64_filter) {
+            const double floor_inner = (inner == CSTAR_FP32_BF16LINKS ? 4e-3 : 5e-9) * qscale;
+            if (rabs < 20.0 * floor_inner || stall >= 3) {
+                if (inner == CSTAR_FP32_BF16LINKS)
+                    inner = CSTAR_FP32;
+                else
+                    fp64_filter = true;
+                stall = 0;
+            }
         }
         // filter degree: about two e-folds of damping per iteration between the
-        // wanted Ritz values and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up)
-        if (o.degree <= 0 && (int)theta.size() >= 2 * k) {
-            const double gap = acut - theta[2 * k - 1];
-            if (gap > 0) {
-                const double want = std::ceil(2.0 / (2.0 * std::sqrt(gap / bup)));
-                deg = (int)std::min<double>(deg_max, std::max<double>(16.0, want));
-            } else if (stall) {
-                deg = std::min(deg_max, deg + deg / 2);
+        // slowest wanted Ritz value and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up),
+        // but bounded so that the filter's gain across the wanted values stays
+        // below 1e4 (inner precision) / 1e8 (FP64): a larger spread lets the
+        // lowest mode swamp every column of the filtered block.
+        if (o.degree <= 0) {
+            if (it < 2 || (int)theta.size() < 2 * k) {
+                deg = 16;
+            } else {
+                const double gk = std::max(acut - theta[2 * k - 1], 1e-300);
+                const double g0 = std::max(acut - theta[0], gk);
+                const double sk = std::sqrt(gk / bup), s0 = std::sqrt(g0 / bup);
+                const double d_want = 1.0 / sk;
+                const double d_range = std::log(fp64_filter ? 1e8 : 1e4) / (2.0 * (s0 - sk) + 1e-300);
+                deg = (int)std::min<double>(deg_max, std::max<double>(8.0, std::min(d_want, d_range)));
             }
-        } else if (stall && deg < deg_max) {
-            deg = std::min(deg_max, deg + deg / 2);
         }
-        last_rmax = rmax;
         last_rabs = rabs;
     }
     CSTAR_HIP(hipStreamSynchronize(c.s));

@@ -34,9 +34,12 @@ __global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, lon
     const long chunk = (n + gridDim.x - 1) / gridDim.x;
     const long n0 = (long)blockIdx.x * chunk;
     const long n1 = n0 + chunk < n ? n0 + chunk : n;
+    // V^H V: stage the block once and read both operands from it
+    const bool sym = (V == W) && (nv == nw) && (ldv == ldw);
+    double2(*sWp)[GNC + 1] = sym ? sV : sW;
     for (long base = n0; base < n1; base += GNC) {
         // stage GNC entries of every vector
-        for (int e = tid; e < (nv + nw) * GNC; e += 256) {
+        for (int e = tid; e < (sym ? nv : nv + nw) * GNC; e += 256) {
             const int vec = e / GNC, off = e % GNC;
             const long idx = base + off;
             double2 val = make_double2(0.0, 0.0);
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, lon
             for (int a = 0; a < 4; a++) {
                 const int i = ti + 16 * a, j = tj + 16 * a;
                 v[a] = i < nv ? sV[i][k] : make_double2(0.0, 0.0);
-                w[a] = j < nw ? sW[j][k] : make_double2(0.0, 0.0);
+                w[a] = j < nw ? sWp[j][k] : make_double2(0.0, 0.0);
             }
 #pragma unroll
             for (int a = 0; a < 4; a++)
@@ -104,11 +107,12 @@ hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, lon
     return hipGetLastError();
 }
 
-// Out_j[n] = sum_i V_i[n] C[i*ldc + j]  (i < nv, j < no), C complex in device memory
-constexpr int CJ = 8;
+// Out_j[n] = beta * Out_j[n] + sum_i V_i[n] C[i*ldc + j]  (i < nv, j < no), C in device memory.
+// CJ output columns per pass (chosen >= no so that V is read once).
+template <int CJ>
 __global__ __launch_bounds__(256) void k_combine(const double2 *__restrict__ V, long ldv, int nv,
                                                  const double2 *__restrict__ C, int ldc, double2 *__restrict__ O,
-                                                 long ldo, int no, long n) {
+                                                 long ldo, int no, long n, double beta) {
     __shared__ double2 sC[128 * CJ];
     const int j0 = blockIdx.y * CJ;
     for (int e = threadIdx.x; e < nv * CJ; e += blockDim.x) {
@@ -116,6 +120,7 @@ __global__ __launch_bounds__(256) void k_combine(const double2 *__restrict__ V, 
         sC[e] = (j0 + jj < no) ? C[i * ldc + j0 + jj] : make_double2(0.0, 0.0);
     }
     __syncthreads();
+    const int nj = no - j0 < CJ ? no - j0 : CJ;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
         double2 acc[CJ];
 #pragma unroll
@@ -125,22 +130,35 @@ __global__ __launch_bounds__(256) void k_combine(const double2 *__restrict__ V, 
 #pragma unroll
             for (int jj = 0; jj < CJ; jj++) {
                 const double2 c = sC[i * CJ + jj];
-                acc[jj].x += v.x * c.x - v.y * c.y;
-                acc[jj].y += v.x * c.y + v.y * c.x;
+                acc[jj].x = fma(v.x, c.x, fma(-v.y, c.y, acc[jj].x));
+                acc[jj].y = fma(v.x, c.y, fma(v.y, c.x, acc[jj].y));
             }
         }
 #pragma unroll
         for (int jj = 0; jj < CJ; jj++)
-            if (j0 + jj < no) O[(long)(j0 + jj) * ldo + idx] = acc[jj];
+            if (jj < nj) {
+                double2 *o = O + (long)(j0 + jj) * ldo + idx;
+                if (beta != 0.0) {
+                    const double2 old = *o;
+                    acc[jj].x += beta * old.x;
+                    acc[jj].y += beta * old.y;
+                }
+                *o = acc[jj];
+            }
     }
 }
 
 hipError_t launch_combine(const double2 *V, long ldv, int nv, const double2 *C_dev, int ldc, double2 *O, long ldo,
-                          int no, long n, hipStream_t s) {
+                          int no, long n, hipStream_t s, double beta) {
     if (nv > 128) return hipErrorInvalidValue;
     const int gx = 1024;
-    hipLaunchKernelGGL(k_combine, dim3(gx, (no + CJ - 1) / CJ), dim3(256), 0, s, V, ldv, nv, C_dev, ldc, O, ldo, no,
-                       n);
+    if (no <= 8)
+        hipLaunchKernelGGL(k_combine<8>, dim3(gx, 1), dim3(256), 0, s, V, ldv, nv, C_dev, ldc, O, ldo, no, n, beta);
+    else if (no <= 16)
+        hipLaunchKernelGGL(k_combine<16>, dim3(gx, 1), dim3(256), 0, s, V, ldv, nv, C_dev, ldc, O, ldo, no, n, beta);
+    else
+        hipLaunchKernelGGL(k_combine<24>, dim3(gx, (no + 23) / 24), dim3(256), 0, s, V, ldv, nv, C_dev, ldc, O, ldo,
+                           no, n, beta);
     return hipGetLastError();
 }
 

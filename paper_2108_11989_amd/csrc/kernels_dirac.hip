@@ -45,20 +45,53 @@ template <class R>
 __device__ __forceinline__ cx<R> mul_mi(cx<R> a) { return {a.im, -a.re}; }
 template <class R>
 __device__ __forceinline__ cx<R> cj(cx<R> a) { return {a.re, -a.im}; }
+// fused complex multiply-accumulate: acc + a*b, acc + conj(a)*b (four FMAs each)
+template <class R>
+__device__ __forceinline__ cx<R> cmac(cx<R> acc, cx<R> a, cx<R> b) {
+    return {fma(-a.im, b.im, fma(a.re, b.re, acc.re)), fma(a.im, b.re, fma(a.re, b.im, acc.im))};
+}
+template <class R>
+__device__ __forceinline__ cx<R> cmac_conj(cx<R> acc, cx<R> a, cx<R> b) {
+    return {fma(a.im, b.im, fma(a.re, b.re, acc.re)), fma(-a.im, b.re, fma(a.re, b.im, acc.im))};
+}
+// a*b - c*d
+template <class R>
+__device__ __forceinline__ cx<R> cmul_sub(cx<R> a, cx<R> b, cx<R> c, cx<R> d) {
+    const cx<R> t = {c.re * d.re - c.im * d.im, c.re * d.im + c.im * d.re};
+    return cmac(cx<R>{-t.re, -t.im}, a, b);
+}
 
 // ---------------------------------------------------------------- geometry
+// LOG2L > 0: L = 2^LOG2L known at compile time (shifts); 0: runtime L.
+template <int LOG2L>
 __device__ __forceinline__ void decode(const Geo &g, int p, int h, int &t, int &x1, int &x2, int &x3) {
-    int r = h;
-    const int x3h = r % g.Lh;
-    r /= g.Lh;
-    x2 = r % g.L;
-    r /= g.L;
-    x1 = r % g.L;
-    t = r / g.L;
+    int x3h;
+    if constexpr (LOG2L > 0) {
+        constexpr int L = 1 << LOG2L, Lh = L / 2;
+        x3h = h & (Lh - 1);
+        int r = h >> (LOG2L - 1);
+        x2 = r & (L - 1);
+        r >>= LOG2L;
+        x1 = r & (L - 1);
+        t = r >> LOG2L;
+    } else {
+        int r = h;
+        x3h = r % g.Lh;
+        r /= g.Lh;
+        x2 = r % g.L;
+        r /= g.L;
+        x1 = r % g.L;
+        t = r / g.L;
+    }
     x3 = 2 * x3h + ((p + t + x1 + x2) & 1);
 }
+template <int LOG2L>
 __device__ __forceinline__ int pair_index(const Geo &g, int t, int x1, int x2, int x3) {
-    return (((t * g.L + x1) * g.L + x2) * g.L + x3) >> 1;
+    if constexpr (LOG2L > 0) return ((((((t << LOG2L) + x1) << LOG2L) + x2) << LOG2L) + x3) >> 1;
+    else return (((t * g.L + x1) * g.L + x2) * g.L + x3) >> 1;
+}
+__device__ __forceinline__ void decode(const Geo &g, int p, int h, int &t, int &x1, int &x2, int &x3) {
+    decode<0>(g, p, h, t, x1, x2, x3);
 }
 
 struct Hop {
@@ -67,23 +100,25 @@ struct Hop {
     int tw;    // 1 if the hop wraps in time
 };
 
-template <int MU>
+template <int MU, int LOG2L>
 __device__ __forceinline__ Hop hop_fwd(const Geo &g, int t, int x1, int x2, int x3) {
+    const int L = LOG2L > 0 ? (1 << LOG2L) : g.L;
     int flip = 0, tw = 0;
     if (MU == 0) { t += 1; if (t == g.T) { t = 0; tw = 1; } }
-    if (MU == 1) { x1 += 1; if (x1 == g.L) { x1 = 0; flip = 1; } }
-    if (MU == 2) { x2 += 1; if (x2 == g.L) { x2 = 0; flip = 1; } }
-    if (MU == 3) { x3 += 1; if (x3 == g.L) { x3 = 0; flip = 1; } }
-    return {pair_index(g, t, x1, x2, x3), flip, tw};
+    if (MU == 1) { x1 += 1; if (x1 == L) { x1 = 0; flip = 1; } }
+    if (MU == 2) { x2 += 1; if (x2 == L) { x2 = 0; flip = 1; } }
+    if (MU == 3) { x3 += 1; if (x3 == L) { x3 = 0; flip = 1; } }
+    return {pair_index<LOG2L>(g, t, x1, x2, x3), flip, tw};
 }
-template <int MU>
+template <int MU, int LOG2L>
 __device__ __forceinline__ Hop hop_bwd(const Geo &g, int t, int x1, int x2, int x3) {
+    const int L = LOG2L > 0 ? (1 << LOG2L) : g.L;
     int flip = 0, tw = 0;
     if (MU == 0) { if (t == 0) { t = g.T; tw = 1; } t -= 1; }
-    if (MU == 1) { if (x1 == 0) { x1 = g.L; flip = 1; } x1 -= 1; }
-    if (MU == 2) { if (x2 == 0) { x2 = g.L; flip = 1; } x2 -= 1; }
-    if (MU == 3) { if (x3 == 0) { x3 = g.L; flip = 1; } x3 -= 1; }
-    return {pair_index(g, t, x1, x2, x3), flip, tw};
+    if (MU == 1) { if (x1 == 0) { x1 = L; flip = 1; } x1 -= 1; }
+    if (MU == 2) { if (x2 == 0) { x2 = L; flip = 1; } x2 -= 1; }
+    if (MU == 3) { if (x3 == 0) { x3 = L; flip = 1; } x3 -= 1; }
+    return {pair_index<LOG2L>(g, t, x1, x2, x3), flip, tw};
 }
 
 // ---------------------------------------------------------------- spinor storage
@@ -151,9 +186,9 @@ __device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 
 template <class R>
 __device__ __forceinline__ void row2_from_rows(cx<R> u[9]) {
     // row 2 = conj(row0 x row1)
-    u[6] = cj(u[1] * u[5] - u[2] * u[4]);
-    u[7] = cj(u[2] * u[3] - u[0] * u[5]);
-    u[8] = cj(u[0] * u[4] - u[1] * u[3]);
+    u[6] = cj(cmul_sub(u[1], u[5], u[2], u[4]));
+    u[7] = cj(cmul_sub(u[2], u[3], u[0], u[5]));
+    u[8] = cj(cmul_sub(u[0], u[4], u[1], u[3]));
 }
 
 struct FmtF64 {
@@ -217,13 +252,13 @@ __device__ __forceinline__ void link_mul(const Link<R> &L, const cx<R> h[6], cx<
     for (int s = 0; s < 2; s++) {
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            cx<R> acc = {R(0), R(0)};
+            cx<R> acc = DAG ? conjmul(L.u[i], h[s * 3]) : L.u[i * 3] * h[s * 3];
 #pragma unroll
-            for (int j = 0; j < 3; j++) {
+            for (int j = 1; j < 3; j++) {
                 if (DAG)
-                    acc = acc + conjmul(L.u[j * 3 + i], h[s * 3 + j]);
+                    acc = cmac_conj(acc, L.u[j * 3 + i], h[s * 3 + j]);
                 else
-                    acc = acc + L.u[i * 3 + j] * h[s * 3 + j];
+                    acc = cmac(acc, L.u[i * 3 + j], h[s * 3 + j]);
             }
             if (Fmt::has_phase) acc = DAG ? conjmul(L.ph, acc) : L.ph * acc;
             o[s * 3 + i] = acc;
@@ -254,30 +289,27 @@ __device__ __forceinline__ void project(const cx<R> v[12], cx<R> h[6]) {
     }
 }
 
-// acc += f * (1 + SG g_mu)-reconstruction of the transported half spinor g
+// acc += (1 + SG g_mu)-reconstruction of the transported half spinor g
 template <int MU, int SG, class R>
-__device__ __forceinline__ void accumulate(cx<R> acc[12], const cx<R> g[6], R f) {
+__device__ __forceinline__ void accumulate(cx<R> acc[12], const cx<R> g[6]) {
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const cx<R> g0 = scale(g[a], f), g1 = scale(g[3 + a], f);
+        const cx<R> g0 = g[a], g1 = g[3 + a];
         acc[a] = acc[a] + g0;
         acc[3 + a] = acc[3 + a] + g1;
-        cx<R> r2, r3;
         if (MU == 0) {
-            r2 = SG < 0 ? g0 : mk(-g0.re, -g0.im);
-            r3 = SG < 0 ? g1 : mk(-g1.re, -g1.im);
+            acc[6 + a] = SG < 0 ? acc[6 + a] + g0 : acc[6 + a] - g0;
+            acc[9 + a] = SG < 0 ? acc[9 + a] + g1 : acc[9 + a] - g1;
         } else if (MU == 1) {
-            r2 = SG < 0 ? mul_mi(g1) : mul_i(g1);
-            r3 = SG < 0 ? mul_mi(g0) : mul_i(g0);
+            acc[6 + a] = acc[6 + a] + (SG < 0 ? mul_mi(g1) : mul_i(g1));
+            acc[9 + a] = acc[9 + a] + (SG < 0 ? mul_mi(g0) : mul_i(g0));
         } else if (MU == 2) {
-            r2 = SG < 0 ? mk(-g1.re, -g1.im) : g1;
-            r3 = SG < 0 ? g0 : mk(-g0.re, -g0.im);
+            acc[6 + a] = SG < 0 ? acc[6 + a] - g1 : acc[6 + a] + g1;
+            acc[9 + a] = SG < 0 ? acc[9 + a] + g0 : acc[9 + a] - g0;
         } else {
-            r2 = SG < 0 ? mul_mi(g0) : mul_i(g0);
-            r3 = SG < 0 ? mul_i(g1) : mul_mi(g1);
+            acc[6 + a] = acc[6 + a] + (SG < 0 ? mul_mi(g0) : mul_i(g0));
+            acc[9 + a] = acc[9 + a] + (SG < 0 ? mul_i(g1) : mul_mi(g1));
         }
-        acc[6 + a] = acc[6 + a] + r2;
-        acc[9 + a] = acc[9 + a] + r3;
     }
 }
 
@@ -331,8 +363,8 @@ __device__ __forceinline__ void herm6_mul(const R dg[6], const cx<R> o[15], cons
         cx<R> acc = scale(u[i], dg[i]);
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            if (j < i) acc = acc + o[i * (i - 1) / 2 + j] * u[j];
-            if (j > i) acc = acc + conjmul(o[j * (j - 1) / 2 + i], u[j]);
+            if (j < i) acc = cmac(acc, o[i * (i - 1) / 2 + j], u[j]);
+            if (j > i) acc = cmac_conj(acc, o[j * (j - 1) / 2 + i], u[j]);
         }
         w[i] = acc;
     }
@@ -357,34 +389,44 @@ struct Prec<FmtBF16> {
     using V = float4;
 };
 
-template <class Fmt, int MU>
+// Hopping sum of one direction (both hops), accumulated without the -1/2
+// (applied once per site); the antiperiodic time sign flips the projected
+// half spinor of a wrapping hop.
+template <class Fmt, int MU, int LOG2L>
 __device__ __forceinline__ void hop_pair(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
                                          int p, int h, int c, int t, int x1, int x2, int x3,
                                          cx<typename Prec<Fmt>::R> acc[12]) {
     using R = typename Prec<Fmt>::R;
-    const R half = R(-0.5);
-    {  // forward: -1/2 (1 - g_mu) V(x,mu) psi(x+mu)
-        const Hop n = hop_fwd<MU>(g, t, x1, x2, x3);
+    {  // forward: (1 - g_mu) V(x,mu) psi(x+mu)
+        const Hop n = hop_fwd<MU, LOG2L>(g, t, x1, x2, x3);
         Link<R> L;
         Fmt::load(d, g, p, MU, h, c ? R(-1) : R(1), L);
         cx<R> v[12], hh[6], gg[6];
         SpinorIO<R>::load(in, g, 1 - p, n.h, c ^ n.flip, v);
         project<MU, -1>(v, hh);
+        if (MU == 0) {
+            const R sg = (n.tw && g.time_bc < 0) ? R(-1) : R(1);
+#pragma unroll
+            for (int i = 0; i < 6; i++) hh[i] = scale(hh[i], sg);
+        }
         link_mul<Fmt, false>(L, hh, gg);
-        const R f = (n.tw && g.time_bc < 0) ? -half : half;
-        accumulate<MU, -1>(acc, gg, f);
+        accumulate<MU, -1>(acc, gg);
     }
-    {  // backward: -1/2 (1 + g_mu) V(x-mu,mu)^H psi(x-mu)
-        const Hop n = hop_bwd<MU>(g, t, x1, x2, x3);
+    {  // backward: (1 + g_mu) V(x-mu,mu)^H psi(x-mu)
+        const Hop n = hop_bwd<MU, LOG2L>(g, t, x1, x2, x3);
         const int cn = c ^ n.flip;
         Link<R> L;
         Fmt::load(d, g, 1 - p, MU, n.h, cn ? R(-1) : R(1), L);
         cx<R> v[12], hh[6], gg[6];
         SpinorIO<R>::load(in, g, 1 - p, n.h, cn, v);
         project<MU, 1>(v, hh);
+        if (MU == 0) {
+            const R sg = (n.tw && g.time_bc < 0) ? R(-1) : R(1);
+#pragma unroll
+            for (int i = 0; i < 6; i++) hh[i] = scale(hh[i], sg);
+        }
         link_mul<Fmt, true>(L, hh, gg);
-        const R f = (n.tw && g.time_bc < 0) ? -half : half;
-        accumulate<MU, 1>(acc, gg, f);
+        accumulate<MU, 1>(acc, gg);
     }
 }
 
@@ -427,36 +469,121 @@ __device__ __forceinline__ void pin(cx<R> acc[12]) {
     for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
 }
 
-// One site of the x-doubled lattice (lane = pair x copy), one right-hand side.
-template <class Fmt>
+// Epilogue of a launch: out = a * ([g5] D psi) + b * y + c * z, with y and z
+// spinor blocks of the output's layout (used by the Chebyshev recurrence to
+// form its three-term update without another pass over memory).
+template <class V>
+struct Epi {
+    const V *y, *z;
+    float a, b, c;      // FP32 forms
+    double ad, bd, cd;  // FP64 form
+    int on;
+};
+
+// One site of the x-doubled lattice (lane = pair x copy), one right-hand side:
+// out = (4+m) chi + SW chi - 1/2 (hopping sum), optionally times g5.
+template <class Fmt, int LOG2L>
 __device__ __forceinline__ void site_apply(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
                                            typename Prec<Fmt>::V *__restrict__ out, int p, int h, int c, int t, int x1,
-                                           int x2, int x3, double mass, int gamma5) {
+                                           int x2, int x3, double mass, int gamma5,
+                                           const Epi<typename Prec<Fmt>::V> &ep, long joff) {
     using R = typename Prec<Fmt>::R;
     cx<R> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = {R(0), R(0)};
-    // scheduling fences between directions bound the live loads (and registers)
-    // to one direction's two hops
-    hop_pair<Fmt, 0>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    // the pins between directions bound the live loads (and registers) to one
+    // direction's two hops
+    hop_pair<Fmt, 0, LOG2L>(g, d, in, p, h, c, t, x1, x2, x3, acc);
     pin(acc);
-    hop_pair<Fmt, 1>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    hop_pair<Fmt, 1, LOG2L>(g, d, in, p, h, c, t, x1, x2, x3, acc);
     pin(acc);
-    hop_pair<Fmt, 2>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    hop_pair<Fmt, 2, LOG2L>(g, d, in, p, h, c, t, x1, x2, x3, acc);
     pin(acc);
-    hop_pair<Fmt, 3>(g, d, in, p, h, c, t, x1, x2, x3, acc);
+    hop_pair<Fmt, 3, LOG2L>(g, d, in, p, h, c, t, x1, x2, x3, acc);
     pin(acc);
     cx<R> chi[12];
     SpinorIO<R>::load(in, g, p, h, c, chi);
-    clover_add<R>(d, g, p, h, c, chi, acc);
+    cx<R> sw[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) sw[k] = {R(0), R(0)};
+    clover_add<R>(d, g, p, h, c, chi, sw);
     const R dm = R(4.0 + mass);
+    const R mh = R(-0.5);
+    const R s5 = gamma5 ? R(-1) : R(1);
 #pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = acc[k] + scale(chi[k], dm);
-    if (gamma5) {
+    for (int k = 0; k < 12; k++) {
+        cx<R> o = sw[k] + scale(chi[k], dm);
+        o = {o.re + mh * acc[k].re, o.im + mh * acc[k].im};
+        if (k >= 6) o = scale(o, s5);
+        acc[k] = o;
+    }
+    if (ep.on) {
+        cx<R> yv[12], zv[12];
+        SpinorIO<R>::load(ep.y + joff, g, p, h, c, yv);
+        SpinorIO<R>::load(ep.z + joff, g, p, h, c, zv);
+        const R a = sizeof(R) == 8 ? R(ep.ad) : R(ep.a);
+        const R b = sizeof(R) == 8 ? R(ep.bd) : R(ep.b);
+        const R cc = sizeof(R) == 8 ? R(ep.cd) : R(ep.c);
 #pragma unroll
-        for (int k = 6; k < 12; k++) acc[k] = mk(-acc[k].re, -acc[k].im);
+        for (int k = 0; k < 12; k++)
+            acc[k] = {fma(cc, zv[k].re, fma(b, yv[k].re, a * acc[k].re)),
+                      fma(cc, zv[k].im, fma(b, yv[k].im, a * acc[k].im))};
     }
     SpinorIO<R>::store(out, g, p, h, c, acc);
+}
+
+// Site of lane `lane` of logical tile `tile` (a tile = one workgroup of 256
+// lanes = 128 pairs x 2 copies).
+//  - plain order (any L): 128 consecutive pairs of the even/odd index;
+//  - blocked order (L = 16, 32, 64): a tile is 16 x2-rows x 8 x3-pairs at
+//    fixed (parity, t, x1); tiles run over (x1 in a block of 4, then t, then
+//    the spatial region, x1-blocks fastest, then parity).  Consecutive tiles
+//    walk the time direction of one compact spatial region, so the t+-1
+//    neighbours -- 16K pairs apart in memory -- are fetched while still in the
+//    XCD's L2, and consecutive regions share their x1 face.
+template <int LOG2L>
+__device__ __forceinline__ bool tile_site(const Geo &g, int tile, int lane, int &p, int &h, int &c, int &t, int &x1,
+                                          int &x2, int &x3) {
+    c = lane & 1;
+    if constexpr (LOG2L >= 4) {
+        constexpr int L = 1 << LOG2L, Lh = L / 2;
+        constexpr int nx3b = Lh / 8, nx2b = L / 16, nx1b = L / 4;
+        int r = tile;
+        const int x1_in = r & 3;
+        r >>= 2;
+        t = r % g.T;
+        r /= g.T;
+        const int x1b = r % nx1b;
+        r /= nx1b;
+        const int x2b = r % nx2b;
+        r /= nx2b;
+        const int x3b = r % nx3b;
+        p = r / nx3b;
+        if (p > 1) return false;
+        const int pr = lane >> 1;
+        x1 = x1b * 4 + x1_in;
+        x2 = x2b * 16 + (pr >> 3);
+        const int x3h = x3b * 8 + (pr & 7);
+        x3 = 2 * x3h + ((p + t + x1 + x2) & 1);
+        h = pair_index<LOG2L>(g, t, x1, x2, x3);
+        return true;
+    } else {
+        const int gid = tile * 256 + lane;
+        if (gid >= 4 * g.Vh) return false;
+        const int pair = gid >> 1;
+        p = pair >= g.Vh;
+        h = pair - p * g.Vh;
+        decode<LOG2L>(g, p, h, t, x1, x2, x3);
+        return true;
+    }
+}
+
+// Workgroup w of a launch handles logical tile (w mod 8) * (nwg/8) + w/8:
+// the hardware deals workgroups round-robin over the eight XCDs (w mod 8) and
+// each XCD has its own L2, so every XCD gets one contiguous range of tiles.
+__device__ __forceinline__ int xcd_tile(int nwg) {
+    const int w = blockIdx.x;
+    return (w & 7) * (nwg >> 3) + (w >> 3);
 }
 
 // Occupancy target of the apply kernels: FP32 forms at <= 128 VGPRs (4 waves
@@ -470,43 +597,127 @@ struct Occ<FmtF64> {
     static constexpr int waves = 2;
 };
 
-// One launch for nrhs right-hand sides (each with its own mass).  Workgroup
-// w of the launch is mapped to the logical item (tile, rhs) so that the eight
-// XCDs each own a contiguous range of tiles with all their right-hand sides:
-// the hardware hands out workgroups round-robin over the XCDs (w mod 8), and
-// each XCD has its own L2, so the link and clover words of a tile -- and the
-// neighbour spinors shared between adjacent tiles -- are fetched from HBM once
-// per XCD instead of once per right-hand side.
-template <class Fmt>
+// Single right-hand side.
+template <class Fmt, int LOG2L>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::waves))) void k_apply(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
-    long stride, int nrhs, int ntiles, int gamma5, const double *__restrict__ masses, double mass0) {
-    const int nwg = gridDim.x;  // a multiple of 8
-    const int w = blockIdx.x;
-    const int logical = (w & 7) * (nwg >> 3) + (w >> 3);
-    if (logical >= ntiles * nrhs) return;
-    const int tile = logical / nrhs;
-    const int j = logical - tile * nrhs;
-    const int gid = tile * 256 + threadIdx.x;
-    if (gid >= 4 * g.Vh) return;
+    int ntiles, int gamma5, double mass, Epi<typename Prec<Fmt>::V> ep) {
+    const int tile = xcd_tile(gridDim.x);
+    if (tile >= ntiles) return;
+    int p, h, c, t, x1, x2, x3;
+    if (!tile_site<LOG2L>(g, tile, threadIdx.x, p, h, c, t, x1, x2, x3)) return;
+    site_apply<Fmt, LOG2L>(g, d, in, out, p, h, c, t, x1, x2, x3, mass, gamma5, ep, 0);
+}
+
+// Time-column form (L = 2^LOG2L): a lane owns one spatial site (one copy)
+// and walks TC consecutive time slices, so psi(t-1), psi(t), psi(t+1) of its
+// column -- a whole slice apart in memory, far beyond reach of the L2 once
+// every site of a slice is in flight -- are touched by the same lane within
+// a few hundred cycles and come from its CU's caches.  Lanes alternate the
+// spatial parity sp = (x1+x2+x3) mod 2 every copy pair, so the spatial
+// neighbours of a lane are the own sites of its wave-mates.  Right-hand sides
+// run over the grid: launch item = (rhs, lane block), rhs outermost.
+template <class Fmt, int LOG2L, int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::waves))) void k_apply_tcol(
+    Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
+    long stride, int nrhs, int nblk_per_rhs, int gamma5, const double *__restrict__ masses, double mass0,
+    Epi<typename Prec<Fmt>::V> ep) {
+    constexpr int L = 1 << LOG2L, Lh = L / 2, L3h = L * L * L / 2;
+    const int item = xcd_tile(gridDim.x);
+    const int j = item / nblk_per_rhs;
+    if (j >= nrhs) return;
+    const int gid = (item - j * nblk_per_rhs) * 256 + threadIdx.x;
     const int c = gid & 1;
-    const int pair = gid >> 1;
-    const int p = pair >= g.Vh;
-    const int h = pair - p * g.Vh;
-    int t, x1, x2, x3;
-    decode(g, p, h, t, x1, x2, x3);
+    const int sp = (gid >> 1) & 1;
+    const int r = gid >> 2;
+    const int hs = r % L3h;
+    const int b = r / L3h;
+    if (b * TC >= g.T) return;
+    const int x1 = hs / (Lh * L);
+    const int x2 = (hs / Lh) & (L - 1);
+    const int x3 = 2 * (hs & (Lh - 1)) + ((sp + x1 + x2) & 1);
     const double m = masses ? masses[j] : mass0;
-    site_apply<Fmt>(g, d, in + j * stride, out + j * stride, p, h, c, t, x1, x2, x3, m, gamma5);
+    const typename Prec<Fmt>::V *inj = in + j * stride;
+    typename Prec<Fmt>::V *outj = out + j * stride;
+#pragma nounroll
+    for (int k = 0; k < TC; k++) {
+        const int t = b * TC + k;
+        const int p = (t + sp) & 1;
+        const int h = t * L3h + hs;
+        // opaque spatial coordinates: the neighbour indices are recomputed per
+        // slice rather than held (and spilled) across the loop
+        int cj_ = c, x1j = x1, x2j = x2, x3j = x3;
+        asm volatile("" : "+v"(cj_), "+v"(x1j), "+v"(x2j), "+v"(x3j));
+        site_apply<Fmt, LOG2L>(g, d, inj, outj, p, h, cj_, t, x1j, x2j, x3j, m, gamma5, ep, j * stride);
+    }
+}
+
+// nrhs right-hand sides, each with its own mass (lattices without a
+// power-of-two L): every lane applies all of them to its site in turn.
+template <class Fmt, int LOG2L>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::waves))) void k_apply_multi(
+    Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
+    long stride, int nrhs, int ntiles, int gamma5, const double *__restrict__ masses, double mass0,
+    Epi<typename Prec<Fmt>::V> ep) {
+    const int tile = xcd_tile(gridDim.x);
+    if (tile >= ntiles) return;
+    int p, h, c, t, x1, x2, x3;
+    if (!tile_site<LOG2L>(g, tile, threadIdx.x, p, h, c, t, x1, x2, x3)) return;
+#pragma nounroll
+    for (int j = 0; j < nrhs; j++) {
+        const double m = masses ? masses[j] : mass0;
+        // opaque copies of the gauge pointers and coordinates: keeps the
+        // compiler from hoisting loop-invariant loads and indices (and spilling)
+        GaugeDev dj = d;
+        asm volatile("" : "+s"(dj.link64), "+s"(dj.link32), "+s"(dj.linkbf_a), "+s"(dj.linkbf_b));
+        asm volatile("" : "+s"(dj.phase32), "+s"(dj.clov64), "+s"(dj.clov32));
+        int pj = p, hj = h, cj_ = c, tj = t, x1j = x1, x2j = x2, x3j = x3;
+        asm volatile("" : "+v"(pj), "+v"(hj), "+v"(cj_), "+v"(tj), "+v"(x1j), "+v"(x2j), "+v"(x3j));
+        site_apply<Fmt, LOG2L>(g, dj, in + j * stride, out + j * stride, pj, hj, cj_, tj, x1j, x2j, x3j, m, gamma5, ep,
+                               j * stride);
+    }
+}
+
+template <class Fmt, int LOG2L>
+static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
+    using V = typename Prec<Fmt>::V;
+    Epi<V> ep{(const V *)a.y, (const V *)(a.z ? a.z : a.y), (float)a.ea, (float)a.eb, (float)(a.z ? a.ec : 0.0),
+              a.ea, a.eb, a.z ? a.ec : 0.0, a.y ? 1 : 0};
+    const long st = a.stride / (long)sizeof(V);
+    const int ntiles = (4 * g.Vh + 255) / 256;
+    if constexpr (LOG2L >= 2) {
+        // lanes per right-hand side: 2 L^3 (sites x copies) x T / TC
+        const long lanes = 2L * (1L << (3 * LOG2L)) * (g.T % 4 == 0 ? g.T / 4 : g.T / 2);
+        const int nblk = (int)((lanes + 255) / 256);
+        const long items = (long)nblk * a.nrhs;
+        const int nwg = (int)((items + 7) / 8 * 8);
+        if (g.T % 4 == 0)
+            hipLaunchKernelGGL((k_apply_tcol<Fmt, (LOG2L >= 2 ? LOG2L : 2), 4>), dim3(nwg), dim3(256), 0, s, g, d,
+                               (const V *)a.in, (V *)a.out, st, a.nrhs, nblk, a.gamma5, a.masses_dev, a.mass0, ep);
+        else
+            hipLaunchKernelGGL((k_apply_tcol<Fmt, (LOG2L >= 2 ? LOG2L : 2), 2>), dim3(nwg), dim3(256), 0, s, g, d,
+                               (const V *)a.in, (V *)a.out, st, a.nrhs, nblk, a.gamma5, a.masses_dev, a.mass0, ep);
+        return;
+    }
+    const int nwg = (ntiles + 7) / 8 * 8;
+    if (a.nrhs == 1 && !a.masses_dev)
+        hipLaunchKernelGGL((k_apply<Fmt, LOG2L>), dim3(nwg), dim3(256), 0, s, g, d, (const V *)a.in, (V *)a.out,
+                           ntiles, a.gamma5, a.mass0, ep);
+    else
+        hipLaunchKernelGGL((k_apply_multi<Fmt, LOG2L>), dim3(nwg), dim3(256), 0, s, g, d, (const V *)a.in,
+                           (V *)a.out, st, a.nrhs, ntiles, a.gamma5, a.masses_dev, a.mass0, ep);
 }
 
 template <class Fmt>
 static void launch_apply_t(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
-    using V = typename Prec<Fmt>::V;
-    const int ntiles = (4 * g.Vh + 255) / 256;
-    const long items = (long)ntiles * a.nrhs;
-    const int nwg = (int)((items + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_apply<Fmt>, dim3(nwg), dim3(256), 0, s, g, d, (const V *)a.in, (V *)a.out,
-                       a.stride / (long)sizeof(V), a.nrhs, ntiles, a.gamma5, a.masses_dev, a.mass0);
+    switch (g.L) {
+        case 4: launch_apply_l<Fmt, 2>(g, d, a, s); break;
+        case 8: launch_apply_l<Fmt, 3>(g, d, a, s); break;
+        case 16: launch_apply_l<Fmt, 4>(g, d, a, s); break;
+        case 32: launch_apply_l<Fmt, 5>(g, d, a, s); break;
+        case 64: launch_apply_l<Fmt, 6>(g, d, a, s); break;
+        default: launch_apply_l<Fmt, 0>(g, d, a, s); break;
+    }
 }
 
 hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s) {
