@@ -4,9 +4,8 @@
 // base + i*ld.  FP32 native vectors (float4 = two complex entries) are only
 // touched by the elementwise kernels and the precision conversions.
 //
-//  * gram: G[i][j] = sum_n conj(V_i[n]) W_j[n] (FP64), LDS-staged tiles of
-//    both blocks, one partial matrix per workgroup, then a fixed-order sum
-//    over workgroups (bit-reproducible);
+//  * gram: G[i][j] = sum_n conj(V_i[n]) W_j[n] (FP64 matrix cores), one
+//    partial matrix per wave, then a fixed-order sum (bit-reproducible);
 //  * combine: Out_j = sum_i V_i C[i][j] (block rotation / projection);
 //  * lincomb: y = a x + b y + c z elementwise (real a,b,c), FP64 or FP32;
 //  * precision conversion between the FP64 and FP32 native layouts;
@@ -17,68 +16,82 @@
 namespace cstar {
 
 constexpr int GT = 64;   // max vectors per side of one gram tile
-constexpr int GNC = 16;  // entries of n per LDS stage
 
+// Gram tile on the FP64 matrix cores: G = V^H W as real products,
+//   Re G = Vr^T Wr + Vi^T Wi,  Im G = Vr^T Wi - Vi^T Wr,
+// with v_mfma_f64_16x16x4f64 (per instruction D[16x16] += A[16x4] B[4x16];
+// lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[l/16 + 4r][l%16] in register r).  Every wave owns one contiguous range of
+// n and reads its operands straight from memory (16 vectors x 4 consecutive
+// entries per load), writes one partial matrix; the partials are summed in a
+// fixed order afterwards, so the result is bit-reproducible.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int TI, int TJ>
 __global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, long ldv, int nv,
                                               const double2 *__restrict__ W, long ldw, int nw, long n,
                                               double2 *__restrict__ partial) {
-    __shared__ double2 sV[GT][GNC + 1];
-    __shared__ double2 sW[GT][GNC + 1];
-    const int tid = threadIdx.x;
-    const int ti = tid & 15, tj = tid >> 4;
-    double2 acc[4][4];
+    const int lane = threadIdx.x & 63;
+    const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nwv = gridDim.x * 4;
+    long chunk = (n + nwv - 1) / nwv;
+    chunk = (chunk + 7) & ~7L;
+    const long k0 = (long)wv * chunk;
+    const long k1 = k0 + chunk < n ? k0 + chunk : n;
+    const int r = lane & 15, kk = lane >> 4;
+    const bool sym = (V == W) && (ldv == ldw) && (nv == nw) && (TI == TJ);
+    d4v cre[TI][TJ], cim[TI][TJ];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < TI; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = make_double2(0.0, 0.0);
-    const long chunk = (n + gridDim.x - 1) / gridDim.x;
-    const long n0 = (long)blockIdx.x * chunk;
-    const long n1 = n0 + chunk < n ? n0 + chunk : n;
-    // V^H V: stage the block once and read both operands from it
-    const bool sym = (V == W) && (nv == nw) && (ldv == ldw);
-    double2(*sWp)[GNC + 1] = sym ? sV : sW;
-    for (long base = n0; base < n1; base += GNC) {
-        // stage GNC entries of every vector
-        for (int e = tid; e < (sym ? nv : nv + nw) * GNC; e += 256) {
-            const int vec = e / GNC, off = e % GNC;
-            const long idx = base + off;
-            double2 val = make_double2(0.0, 0.0);
-            if (vec < nv) {
-                if (idx < n1) val = V[(long)vec * ldv + idx];
-                sV[vec][off] = val;
+        for (int b = 0; b < TJ; b++) {
+            cre[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+            cim[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll 2
+    for (long k = k0; k < k1; k += 4) {
+        const long kx = k + kk;
+        const bool kin = kx < k1;
+        double vr[TI], vi[TI], wr[TJ], wi[TJ];
+#pragma unroll
+        for (int a = 0; a < TI; a++) {
+            const int i = a * 16 + r;
+            const double2 v = (kin && i < nv) ? V[(long)i * ldv + kx] : make_double2(0.0, 0.0);
+            vr[a] = v.x;
+            vi[a] = v.y;
+        }
+#pragma unroll
+        for (int b = 0; b < TJ; b++) {
+            if (sym) {
+                wr[b] = vr[b < TI ? b : 0];
+                wi[b] = vi[b < TI ? b : 0];
             } else {
-                if (idx < n1) val = W[(long)(vec - nv) * ldw + idx];
-                sW[vec - nv][off] = val;
+                const int j = b * 16 + r;
+                const double2 w = (kin && j < nw) ? W[(long)j * ldw + kx] : make_double2(0.0, 0.0);
+                wr[b] = w.x;
+                wi[b] = w.y;
             }
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < GNC; k++) {
-            double2 v[4], w[4];
 #pragma unroll
-            for (int a = 0; a < 4; a++) {
-                const int i = ti + 16 * a, j = tj + 16 * a;
-                v[a] = i < nv ? sV[i][k] : make_double2(0.0, 0.0);
-                w[a] = j < nw ? sWp[j][k] : make_double2(0.0, 0.0);
+        for (int a = 0; a < TI; a++)
+#pragma unroll
+            for (int b = 0; b < TJ; b++) {
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[a], wr[b], cre[a][b], 0, 0, 0);
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vi[a], wi[b], cre[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[a], wi[b], cim[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-vi[a], wr[b], cim[a][b], 0, 0, 0);
             }
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    acc[a][b].x += v[a].x * w[b].x + v[a].y * w[b].y;
-                    acc[a][b].y += v[a].x * w[b].y - v[a].y * w[b].x;
-                }
-        }
-        __syncthreads();
     }
-    double2 *P = partial + (long)blockIdx.x * GT * GT;
+    double2 *P = partial + (long)wv * GT * GT;
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < TI; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const int i = ti + 16 * a, j = tj + 16 * b;
-            if (i < nv && j < nw) P[i * GT + j] = acc[a][b];
-        }
+        for (int b = 0; b < TJ; b++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int i = a * 16 + kk + 4 * q, j = b * 16 + r;
+                if (i < nv && j < nw) P[i * GT + j] = make_double2(cre[a][b][q], cim[a][b][q]);
+            }
 }
 
 __global__ void k_gram_reduce(const double2 *__restrict__ partial, int nblk, int nv, int nw,
@@ -98,11 +111,29 @@ __global__ void k_gram_reduce(const double2 *__restrict__ partial, int nblk, int
 int gram_blocks() { return 1024; }
 size_t gram_partial_bytes() { return (size_t)gram_blocks() * GT * GT * sizeof(double2); }
 
+template <int TI>
+static void launch_gram_ti(int tj, int nblk, hipStream_t s, const double2 *V, long ldv, int nv, const double2 *W,
+                           long ldw, int nw, long n, double2 *partial) {
+    const dim3 grd(nblk / 4), blk(256);
+    switch (tj) {
+        case 1: hipLaunchKernelGGL((k_gram<TI, 1>), grd, blk, 0, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        case 2: hipLaunchKernelGGL((k_gram<TI, 2>), grd, blk, 0, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        case 3: hipLaunchKernelGGL((k_gram<TI, 3>), grd, blk, 0, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        default: hipLaunchKernelGGL((k_gram<TI, 4>), grd, blk, 0, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+    }
+}
+
 hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, long ldw, int nw, long n,
                        double2 *partial, double2 *out_dev, hipStream_t s) {
-    if (nv > GT || nw > GT) return hipErrorInvalidValue;
-    const int nblk = gram_blocks();
-    hipLaunchKernelGGL(k_gram, dim3(nblk), dim3(256), 0, s, V, ldv, nv, W, ldw, nw, n, partial);
+    if (nv > GT || nw > GT || nv < 1 || nw < 1) return hipErrorInvalidValue;
+    const int nblk = gram_blocks();  // partial matrices = waves of the launch
+    const int ti = (nv + 15) / 16, tj = (nw + 15) / 16;
+    switch (ti) {
+        case 1: launch_gram_ti<1>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        case 2: launch_gram_ti<2>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        case 3: launch_gram_ti<3>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+        default: launch_gram_ti<4>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
+    }
     hipLaunchKernelGGL(k_gram_reduce, dim3((nv * nw + 255) / 256), dim3(256), 0, s, partial, nblk, nv, nw, out_dev);
     return hipGetLastError();
 }
