@@ -43,6 +43,8 @@ def lib():
                                    dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_gammas.argtypes = [dp]
         L.oracle_neighbours.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
+        L.oracle_transport.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -100,6 +102,16 @@ class Operator:
                                 float(m0), int(bool(gamma5)), self.link_mode, _p(psi), _p(out))
         if rc != 0:
             raise MemoryError("oracle_dirac failed")
+        return out
+
+    def transport(self, psi: np.ndarray, mu: int, direction: int) -> np.ndarray:
+        """direction +1: V(x,mu) psi(x+mu); -1: V(x-mu,mu)^H psi(x-mu) (time phase on wrapping hops)."""
+        psi = np.ascontiguousarray(psi, dtype=np.complex128)
+        out = np.empty_like(psi)
+        rc = lib().oracle_transport(self.T, self.L, self.time_bc, self.q, _p(self.su3), _p(self.theta), int(mu),
+                                    int(direction), self.link_mode, _p(psi), _p(out))
+        if rc != 0:
+            raise MemoryError("oracle_transport failed")
         return out
 
     def D(self, psi, m0):

@@ -414,3 +414,40 @@ void oracle_neighbours(int T, int L, long *idx_out) {
             }
     }
 }
+
+/*
+ * Parallel transport used by the gauge-covariant network (oracle side):
+ *   dir = +1: out(x) = ph * V(x,mu) psi(x+mu),   dir = -1: out(x) = ph * V(x-mu,mu)^H psi(x-mu),
+ * colour only (the same 3x3 acts on every spin), ph = time_bc on hops that wrap
+ * in time, V the quark link on the doubled lattice (link_mode as in oracle_dirac).
+ */
+int oracle_transport(int T, int L, int time_bc, double q, const double *su3, const double *theta, int mu,
+                     int dir, int link_mode, const double *in, double *out) {
+    geom g = {T, L, time_bc};
+    long n = n_sites(&g);
+    cplx *Vtab = (cplx *)malloc(sizeof(cplx) * n * 36);
+    if (!Vtab) return -2;
+    build_links(&g, su3, theta, q, link_mode, Vtab);
+    const cplx *psi = (const cplx *)in;
+    cplx *res = (cplx *)out;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        int x[4], y[4], wrap;
+        site_coords(&g, s, x);
+        neighbour(&g, x, mu, dir, y, &wrap);
+        long sy = site_index(&g, y[0], y[1], y[2], y[3]);
+        double ph = wrap ? (double)time_bc : 1.0;
+        cplx W[3][3];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++)
+                W[i][j] = dir > 0 ? Vtab[(s * 4 + mu) * 9 + i * 3 + j] : conj(Vtab[(sy * 4 + mu) * 9 + j * 3 + i]);
+        for (int a = 0; a < 4; a++)
+            for (int i = 0; i < 3; i++) {
+                cplx v = 0;
+                for (int j = 0; j < 3; j++) v += W[i][j] * psi[sy * 12 + a * 3 + j];
+                res[s * 12 + a * 3 + i] = ph * v;
+            }
+    }
+    free(Vtab);
+    return 0;
+}
