@@ -31,16 +31,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(prec: int, nsites2: int, launches: int, rhs: int) -> float:
+def algorithmic_bytes(prec: int, nsites2: int, launches: int, rhs: int, operands: int = 0) -> float:
     """Minimum HBM bytes of the apply launches (per doubled site, per launch):
     every input spinor read once, every output written once, links and clover
-    read once per physical site (shared by its conjugate copy):
-      FP64: 384 B per RHS + (4 links x 144 B + clover 576 B)/2
-      FP32: 192 B per RHS + (4 x (48 B rows + 8 B phase) + clover 288 B)/2
-      FP32 + BF16 links: 192 B per RHS + (4 x (24 B rows + 8 B phase) + 288 B)/2
+    read once per physical site (shared by its conjugate copy), and every
+    extra vector of a fused epilogue (out = a D in + b y + c z) read once:
+      FP64: 384 B per RHS + (4 links x 144 B + clover 576 B)/2, 192 B per operand
+      FP32: 192 B per RHS + (4 x (48 B rows + 8 B phase) + clover 288 B)/2, 96 B per operand
+      FP32 + BF16 links: 192 B per RHS + (4 x (24 B rows + 8 B phase) + 288 B)/2, 96 B per operand
     """
     per_rhs, shared = {0: (384.0, 576.0), 1: (192.0, 256.0), 2: (192.0, 208.0)}[prec]
-    return nsites2 * (per_rhs * rhs + shared * launches)
+    return nsites2 * (per_rhs * rhs + shared * launches + per_rhs / 2 * operands)
 
 
 def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
@@ -189,7 +190,8 @@ def main():
     dom = int(np.argmax(ms))
     launches = sum(t[dom]["launches"] for t in tms)
     rhs = sum(t[dom]["rhs"] for t in tms)
-    byts = algorithmic_bytes(dom, nsites2, launches, rhs)
+    operands = sum(t[dom]["operands"] for t in tms)
+    byts = algorithmic_bytes(dom, nsites2, launches, rhs, operands)
     achieved = byts / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
     kern_name = {0: "apply FP64", 1: "apply FP32", 2: "apply FP32/BF16-links"}[dom]
     log(f"[bench] kernel time by precision (ms): {ms}; dominant {kern_name}: {launches} launches, "

@@ -196,13 +196,16 @@ cstar_status cstar_sign_driver(cstar_eig_provider provider, void *ctx, const dou
  * dirac_apply and by the solvers): when enabled, HIP events are recorded on
  * the handle's stream around every launch.  Per precision p (cstar_prec):
  * launches[p] kernel launches, rhs[p] right-hand sides they applied, ms[p]
- * summed kernel time.  enable(on) resets the counters; read synchronises the
- * stream.  Errors: EINVAL for a null handle; EDEVICE.
+ * summed kernel time, operands[p] extra input vectors read by fused epilogues
+ * (out = a D in + b y + c z reads y and z: two per right-hand side).
+ * enable(on) resets the counters; read synchronises the stream.  Errors:
+ * EINVAL for a null handle; EDEVICE.
  */
 typedef struct {
     long launches[3];
     long rhs[3];
     double ms[3];
+    long operands[3];
 } cstar_apply_timing;
 cstar_status cstar_timing_enable(cstar_gauge *g, int on);
 cstar_status cstar_timing_read(cstar_gauge *g, cstar_apply_timing *out);

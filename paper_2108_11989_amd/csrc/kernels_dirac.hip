@@ -121,6 +121,28 @@ __device__ __forceinline__ Hop hop_bwd(const Geo &g, int t, int x1, int x2, int 
     return {pair_index<LOG2L>(g, t, x1, x2, x3), flip, tw};
 }
 
+// Streaming (non-temporal) access for data used once per launch -- the
+// clover term and the output -- so that it does not evict the spinor and link
+// lines that neighbouring sites read again.
+typedef float ntf4 __attribute__((ext_vector_type(4)));
+typedef double ntd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 load_nt(const float4 *p) {
+    const ntf4 v = __builtin_nontemporal_load(reinterpret_cast<const ntf4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 load_nt(const double2 *p) {
+    const ntd2 v = __builtin_nontemporal_load(reinterpret_cast<const ntd2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void store_nt(float4 a, float4 *p) {
+    const ntf4 v = {a.x, a.y, a.z, a.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<ntf4 *>(p));
+}
+__device__ __forceinline__ void store_nt(double2 a, double2 *p) {
+    const ntd2 v = {a.x, a.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<ntd2 *>(p));
+}
+
 // ---------------------------------------------------------------- spinor storage
 // FP64: double2 [p][12][Vh][2];  FP32: float4 [p][6][Vh][2]
 template <class R>
@@ -144,7 +166,7 @@ struct SpinorIO<double> {
         double2 *q = b + ((long)p * 12 * g.Vh + h) * 2 + c;
         const long st = 2L * g.Vh;
 #pragma unroll
-        for (int k = 0; k < 12; k++) q[k * st] = make_double2(v[k].re, v[k].im);
+        for (int k = 0; k < 12; k++) store_nt(make_double2(v[k].re, v[k].im), &q[k * st]);
     }
 };
 
@@ -167,7 +189,8 @@ struct SpinorIO<float> {
         float4 *q = b + ((long)p * 6 * g.Vh + h) * 2 + c;
         const long st = 2L * g.Vh;
 #pragma unroll
-        for (int k = 0; k < 6; k++) q[k * st] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+        for (int k = 0; k < 6; k++)
+            store_nt(make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im), &q[k * st]);
     }
 };
 
@@ -327,13 +350,13 @@ struct CloverIO<double> {
         const double2 *q = d.clov64 + (long)(p * 36 + b * 18) * g.Vh + h;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const double2 w = q[(long)k * g.Vh];
+            const double2 w = load_nt(&q[(long)k * g.Vh]);
             dg[2 * k] = w.x;
             dg[2 * k + 1] = w.y;
         }
 #pragma unroll
         for (int k = 0; k < 15; k++) {
-            const double2 w = q[(long)(3 + k) * g.Vh];
+            const double2 w = load_nt(&q[(long)(3 + k) * g.Vh]);
             o[k] = {w.x, w.y};
         }
     }
@@ -343,13 +366,13 @@ struct CloverIO<float> {
     static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int h, int b, float dg[6],
                                                 cx<float> o[15]) {
         const float4 *q = d.clov32 + (long)(p * 18 + b * 9) * g.Vh + h;
-        const float4 w0 = q[0], w1 = q[g.Vh];
+        const float4 w0 = load_nt(&q[0]), w1 = load_nt(&q[g.Vh]);
         dg[0] = w0.x; dg[1] = w0.y; dg[2] = w0.z; dg[3] = w0.w;
         dg[4] = w1.x; dg[5] = w1.y;
         o[0] = {w1.z, w1.w};
 #pragma unroll
         for (int k = 0; k < 7; k++) {
-            const float4 w = q[(long)(2 + k) * g.Vh];
+            const float4 w = load_nt(&q[(long)(2 + k) * g.Vh]);
             o[1 + 2 * k] = {w.x, w.y};
             o[2 + 2 * k] = {w.z, w.w};
         }

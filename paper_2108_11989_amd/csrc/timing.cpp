@@ -15,6 +15,7 @@ struct Pending {
 struct Timing {
     long launches[3] = {0, 0, 0};
     long rhs[3] = {0, 0, 0};
+    long operands[3] = {0, 0, 0};
     double ms[3] = {0, 0, 0};
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
@@ -59,6 +60,7 @@ hipError_t handle_apply(cstar_gauge *g, cstar_prec prec, const ApplyArgs &a) {
     t->pending.push_back({ea, eb, (int)prec});
     t->launches[prec] += 1;
     t->rhs[prec] += a.nrhs;
+    if (a.y) t->operands[prec] += (long)a.nrhs * ((a.z && a.ec != 0.0) ? 2 : 1);
     if (t->pending.size() >= 4096) return drain(t);
     return hipSuccess;
 }
@@ -93,6 +95,7 @@ extern "C" cstar_status cstar_timing_read(cstar_gauge *g, cstar_apply_timing *ou
         out->launches[p] = t->launches[p];
         out->rhs[p] = t->rhs[p];
         out->ms[p] = t->ms[p];
+        out->operands[p] = t->operands[p];
     }
     return CSTAR_OK;
 }

@@ -54,7 +54,8 @@ class SignReport(ctypes.Structure):
 
 
 class ApplyTiming(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_long * 3), ("rhs", ctypes.c_long * 3), ("ms", ctypes.c_double * 3)]
+    _fields_ = [("launches", ctypes.c_long * 3), ("rhs", ctypes.c_long * 3), ("ms", ctypes.c_double * 3),
+                ("operands", ctypes.c_long * 3)]
 
 
 PROVIDER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
@@ -172,7 +173,7 @@ class Gauge:
     def read_timing(self) -> dict:
         t = ApplyTiming()
         _check(lib().cstar_timing_read(self.h, ctypes.byref(t)))
-        return {p: dict(launches=t.launches[p], rhs=t.rhs[p], ms=t.ms[p]) for p in range(3)}
+        return {p: dict(launches=t.launches[p], rhs=t.rhs[p], ms=t.ms[p], operands=t.operands[p]) for p in range(3)}
 
     # --- device buffers are torch tensors; the library reads/writes their memory
     def new_native(self, nrhs=1, prec=FP64):
