@@ -131,6 +131,8 @@ typedef struct {
     long applies_inner;      /* single-RHS D applications in the inner precision */
     double seconds;          /* wall time of the call */
     double lambda_max_est;   /* upper spectral bound used by the filter */
+    long nn_applies;         /* network applications (use_nn) */
+    int nn_fallback;         /* 1: the preconditioned solve failed and the plain solver answered */
 } cstar_eig_stats;
 
 /*
@@ -141,7 +143,7 @@ typedef struct {
  * residual norm ||Q v_i - lambda_i v_i|| of a unit vector v_i, a rigorous
  * bound on the distance of lambda_i to the spectrum.  evecs: nullable device
  * pointer, k native FP64 spinors.  stats: nullable.  Synchronous.
- * Errors: EINVAL (k < 1, k > 64), ENOCONV (max_iter reached; evals/resid hold
+ * Errors: EINVAL (k < 1, k > 30), ENOCONV (max_iter reached; evals/resid hold
  * the last iterate), ENOMEM, EDEVICE.
  */
 cstar_status q_lowest_eigs(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts, double *evals,
@@ -162,6 +164,8 @@ typedef struct {
     int n_crossings;     /* certified zero crossings between the target and m_max */
     long applies;        /* single-RHS D applications (all precisions) */
     double seconds;
+    long nn_applies;     /* network applications (opts.eig.use_nn) */
+    int nn_fallbacks;    /* mass points where the plain solver answered for the preconditioned one */
 } cstar_sign_report;
 
 /*
@@ -213,6 +217,59 @@ cstar_status cstar_timing_read(cstar_gauge *g, cstar_apply_timing *out);
 /* Largest spectral norm over sites of the clover term SW(x) (bounds the
  * mass above which Q(m) has no eigenvalue near zero: sigma_min(D) >= m0 - this). */
 cstar_status cstar_clover_norm_max(cstar_gauge *g, double *out);
+
+/*
+ * Learned preconditioner (not part of the paper's method): a gauge-covariant
+ * network M of three linear parallel-transport convolution layers, channels
+ * 1 -> 8 -> 8 -> 1.  A layer maps Cin spinor fields to Cout:
+ *   out_a(x) = sum_b sum_p W[a][b][p] (T_p in_b)(x),
+ * W[a][b][p] a complex 4x4 spin matrix, p = 0 the identity and p = 1 + 2 mu + d
+ * the hop in direction mu (d = 0: V(x,mu) psi(x+mu); d = 1:
+ * V(x-mu,mu)^H psi(x-mu)) on the handle's x-doubled C* lattice with its FP32
+ * links.  It is trained towards (Q^2)^-1, L = (1/N) sum_i |M(Q^2 x_i) - x_i|^2
+ * / |x_i|^2, and used by q_lowest_eigs (opts.use_nn = 1 and a network
+ * attached) on the Ritz block before every inner-precision Chebyshev filter
+ * (the FP64 refinement filters the Ritz block itself), so that identity
+ * weights reproduce the plain iteration; the plain solver answers if the
+ * preconditioned one fails (stats.nn_fallback).
+ *
+ * Weights: CSTAR_NN_PARAMS floats, layers in order, each [Cout][Cin][9][4][4]
+ * complex with (re, im) interleaved.  Vectors: FP32 native spinor blocks
+ * (cstar_spinor_bytes(g, CSTAR_FP32) bytes each) on the device, the handle's
+ * stream.  A network may serve several handles of one device, one at a time.
+ */
+#define CSTAR_NN_PARAMS 23040
+typedef struct cstar_nn cstar_nn;
+
+/* weights: host [CSTAR_NN_PARAMS] or NULL for the identity network.  EINVAL
+ * (non-finite weight), ENOMEM. */
+cstar_status cstar_nn_create(const float *weights, cstar_nn **out);
+void cstar_nn_destroy(cstar_nn *nn);
+cstar_status cstar_nn_get_weights(cstar_nn *nn, float *out);     /* host [CSTAR_NN_PARAMS] */
+cstar_status cstar_nn_set_weights(cstar_nn *nn, const float *w);  /* host [CSTAR_NN_PARAMS] */
+/* y_j = M(b_j), j < nvec.  b and y may be the same block (in place), not
+ * otherwise overlapping.  Asynchronous on the handle's stream. */
+cstar_status cstar_nn_apply(cstar_nn *nn, cstar_gauge *g, int nvec, const void *b, void *y);
+/* Adds to the network's FP64 gradient the gradient of
+ *   (1/n_total) sum_{i<nvec} |M(b_i) - x_i|^2 / |x_i|^2
+ * (gradient g = dL/dRe W + i dL/dIm W, same layout as the weights) and
+ * returns that partial loss.  Synchronous.  EINVAL for a zero x_i. */
+cstar_status cstar_nn_loss_grad(cstar_nn *nn, cstar_gauge *g, int nvec, const void *x, const void *b, int n_total,
+                                double *loss);
+cstar_status cstar_nn_get_grad(cstar_nn *nn, double *out);        /* host [CSTAR_NN_PARAMS] */
+cstar_status cstar_nn_zero_grad(cstar_nn *nn);
+/* One Adam step (bias-corrected) with the accumulated gradient, which is then cleared. */
+cstar_status cstar_nn_adam_step(cstar_nn *nn, double lr, double beta1, double beta2, double eps);
+/* Training on GPU: for every field f (same lattice), b = Q(m0)^2 x in FP32 for
+ * the nvec target vectors x[f] (device FP32 native block); then `epochs`
+ * passes over the fields in order, one Adam step (lr, 0.9, 0.999, 1e-8) per
+ * field on the loss of its nvec pairs.  loss_history: nullable host[epochs],
+ * the mean loss of each pass.  ENOCONV if the loss becomes non-finite. */
+cstar_status cstar_nn_train(cstar_nn *nn, cstar_gauge *const *fields, int n_fields, const void *const *x, int nvec,
+                            double m0, int epochs, double lr, double *loss_history);
+/* Network used by q_lowest_eigs / pfaffian_sign on this handle when
+ * opts.use_nn = 1 (not owned; NULL detaches). */
+cstar_status cstar_nn_attach(cstar_gauge *g, cstar_nn *nn);
 
 #ifdef __cplusplus
 }

@@ -212,25 +212,60 @@ cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_p
     return CSTAR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The learned preconditioner is optional: if the preconditioned solve fails
+// (no convergence or a non-finite result) the plain solver answers.
+cstar_status solve_with_fallback(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts, double *evals,
+                                 double *resid, void *evecs, cstar_eig_stats *stats) {
+    cstar_eig_stats st1{};
+    cstar_status s = eig_lowest(g, m0, k, opts, evals, resid, evecs, &st1);
+    bool bad = s != CSTAR_OK && s != CSTAR_EINVAL;
+    if (s == CSTAR_OK)
+        for (int i = 0; i < k; i++) bad = bad || !std::isfinite(evals[i]);
+    if (opts && opts->use_nn && g->nn && bad) {
+        cstar_eig_opts plain = *opts;
+        plain.use_nn = 0;
+        plain.warm_start = 0;
+        cstar_eig_stats st2{};
+        s = eig_lowest(g, m0, k, &plain, evals, resid, evecs, &st2);
+        st2.applies_fp64 += st1.applies_fp64;
+        st2.applies_inner += st1.applies_inner;
+        st2.seconds += st1.seconds;
+        st2.nn_applies = st1.nn_applies;
+        st2.nn_fallback = 1;
+        st1 = st2;
+    }
+    if (stats) *stats = st1;
+    return s;
+}
+}  // namespace
+
+extern "C" {
+
 cstar_status q_lowest_eigs(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts, double *evals, double *resid,
                            void *evecs, cstar_eig_stats *stats) {
     if (!g || !evals || !std::isfinite(m0)) return fail(CSTAR_EINVAL, "q_lowest_eigs: bad argument");
     if (opts && check_prec(opts->inner)) return CSTAR_EINVAL;
-    return eig_lowest(g, m0, k, opts, evals, resid, evecs, stats, nullptr);
+    return solve_with_fallback(g, m0, k, opts, evals, resid, evecs, stats);
 }
 
 namespace {
 struct GpuProvider {
     cstar_gauge *g;
     cstar_eig_opts opts;
-    long applies = 0;
+    long applies = 0, nn_applies = 0;
+    int fallbacks = 0;
     cstar_status last = CSTAR_OK;
 };
 int gpu_provider(void *ctx, double m, int k, double *evals, double *errs) {
     GpuProvider *p = (GpuProvider *)ctx;
     cstar_eig_stats st{};
-    cstar_status s = eig_lowest(p->g, m, k, &p->opts, evals, errs, nullptr, &st, nullptr);
+    cstar_status s = solve_with_fallback(p->g, m, k, &p->opts, evals, errs, nullptr, &st);
     p->applies += st.applies_fp64 + st.applies_inner;
+    p->nn_applies += st.nn_applies;
+    p->fallbacks += st.nn_fallback;
     p->last = s;
     // later points start from this point's Ritz block: the flow is followed in mass
     p->opts.warm_start = 1;
@@ -250,7 +285,11 @@ cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cs
     const double m_max = opts->m_max > 0 ? opts->m_max : g->clover_norm_max * 1.001 + 1e-3;
     const int k = opts->k > 0 ? opts->k : 4;
     cstar_status st = sign_driver(gpu_provider, &prov, m_path, n, k, c, m_max, sign_out, report);
-    if (report) report->applies = prov.applies;
+    if (report) {
+        report->applies = prov.applies;
+        report->nn_applies = prov.nn_applies;
+        report->nn_fallbacks = prov.fallbacks;
+    }
     if (st == CSTAR_ENOCONV && prov.last != CSTAR_OK) return prov.last;
     return st;
 }

@@ -28,6 +28,7 @@
 #include "cstar_internal.h"
 #include "dense_eig.h"
 #include "eig.h"
+#include "nn.h"
 
 namespace cstar {
 
@@ -95,8 +96,16 @@ struct Ctx {
     Workspace *w;
     hipStream_t s;
     double m;
-    long ap64 = 0, ap_inner = 0;
+    long ap64 = 0, ap_inner = 0, nn_applies = 0;
 };
+
+// Ritz block -> M X in FP32 through the attached network (in place on an FP32 block)
+cstar_status precondition32(Ctx &c, float4 *X32, int nv) {
+    cstar_status st = nn_apply_block(c.g, X32, nv);
+    if (st) return st;
+    c.nn_applies += nv;
+    return CSTAR_OK;
+}
 
 // out = ea * Q in [+ eb * y + ec * z] on nv FP64 vectors
 hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv, double ea = 1.0, const double2 *y = nullptr,
@@ -267,13 +276,17 @@ cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0
 // The same filter in an FP32 form on the F[] buffers: F[0] = X (converted),
 // the result converted back into Yout.
 cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2 *Yout, double a0, double acut,
-                      double bup, int deg) {
+                      double bup, int deg, bool nn) {
     Workspace *w = c.w;
     const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
     const double x0 = (a0 - cen) / e;
     double sig = 1.0 / x0;
     float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
     CSTAR_HIP(launch_to_f32(c.g->geo, nv, X, prev, c.s));
+    if (nn) {
+        cstar_status st = precondition32(c, prev, nv);
+        if (st) return st;
+    }
     CSTAR_HIP(q32(c, prec, prev, tq, nv));
     CSTAR_HIP(q32(c, prec, tq, cur, nv, sig / e, prev, -cen * sig / e));
     for (int j = 1; j < deg; j++) {
@@ -293,7 +306,7 @@ cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2
 }  // namespace
 
 cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *opts_in, double *evals, double *resid,
-                        void *evecs, cstar_eig_stats *stats, const EigHooks *hooks) {
+                        void *evecs, cstar_eig_stats *stats) {
     const auto t_start = std::chrono::steady_clock::now();
     cstar_eig_opts o{};
     o.inner = CSTAR_FP32_BF16LINKS;
@@ -314,6 +327,7 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     if (st) return st;
     Ctx c{g, w, g->stream, m0};
     const long n = w->n;
+    const bool use_nn = o.use_nn && g->nn;
     double2 *X = w->XY, *Y = w->XY + (long)nb * n;
     double2 *AX = w->AXY, *AY = w->AXY + (long)nb * n;
 
@@ -352,14 +366,13 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             // ---- filter: the whole block in the inner precisions; in FP64 only
             // the leading nq vectors (the guard vectors beyond the Q-reduced
             // subspace need no FP64 accuracy)
+            // (with the learned preconditioner M the inner-precision filter acts
+            // on M X; the FP64 refinement filters X itself)
             const int nf = fp64_filter ? nq : nb;
-            if (hooks && hooks->precondition && o.use_nn) {
-                st = hooks->precondition(hooks->ctx, g, m0, X, nf, Y);
-                if (st) return st;
-            } else if (fp64_filter) {
+            if (fp64_filter) {
                 st = filter64(c, X, nf, Y, a0, acut, bup, deg, w->T, w->T2, AY);
             } else {
-                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg);
+                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg, use_nn);
             }
             if (st) return st;
             // ---- orthogonalise against X twice, then orthonormalise within
@@ -570,6 +583,8 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
         stats->applies_inner = c.ap_inner;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         stats->lambda_max_est = bup;
+        stats->nn_applies = c.nn_applies;
+        stats->nn_fallback = 0;
     }
     if (!converged) return fail(CSTAR_ENOCONV, "q_lowest_eigs: max_iter reached");
     return CSTAR_OK;

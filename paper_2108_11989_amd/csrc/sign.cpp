@@ -217,6 +217,8 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             report->lambda_bar[i] = pts[order[i]].lb;
         }
         report->n_crossings = total;
+        report->nn_applies = 0;
+        report->nn_fallbacks = 0;
         report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (st == CSTAR_EAMBIG) return fail(CSTAR_EAMBIG, "pfaffian_sign: an eigenvalue is within its error bound of zero");

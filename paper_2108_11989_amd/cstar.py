@@ -41,7 +41,8 @@ class EigOpts(ctypes.Structure):
 
 class EigStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("applies_fp64", ctypes.c_long), ("applies_inner", ctypes.c_long),
-                ("seconds", ctypes.c_double), ("lambda_max_est", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("lambda_max_est", ctypes.c_double), ("nn_applies", ctypes.c_long),
+                ("nn_fallback", ctypes.c_int)]
 
 
 class SignOpts(ctypes.Structure):
@@ -50,7 +51,8 @@ class SignOpts(ctypes.Structure):
 
 class SignReport(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int), ("m", ctypes.c_double * 512), ("lambda_bar", ctypes.c_double * 512),
-                ("n_crossings", ctypes.c_int), ("applies", ctypes.c_long), ("seconds", ctypes.c_double)]
+                ("n_crossings", ctypes.c_int), ("applies", ctypes.c_long), ("seconds", ctypes.c_double),
+                ("nn_applies", ctypes.c_long), ("nn_fallbacks", ctypes.c_int)]
 
 
 class ApplyTiming(ctypes.Structure):
@@ -91,9 +93,25 @@ def lib():
         L.cstar_clover_norm_max.argtypes = [vp, dp]
         L.cstar_timing_enable.argtypes = [vp, ctypes.c_int]
         L.cstar_timing_read.argtypes = [vp, ctypes.POINTER(ApplyTiming)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.cstar_nn_create.argtypes = [fp, ctypes.POINTER(vp)]
+        L.cstar_nn_destroy.argtypes = [vp]
+        L.cstar_nn_destroy.restype = None
+        L.cstar_nn_get_weights.argtypes = [vp, fp]
+        L.cstar_nn_set_weights.argtypes = [vp, fp]
+        L.cstar_nn_get_grad.argtypes = [vp, dp]
+        L.cstar_nn_zero_grad.argtypes = [vp]
+        L.cstar_nn_apply.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+        L.cstar_nn_loss_grad.argtypes = [vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]
+        L.cstar_nn_adam_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.cstar_nn_train.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
+        L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
                      "q_lowest_eigs", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
-                     "cstar_timing_enable", "cstar_timing_read"):
+                     "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
+                     "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
+                     "cstar_nn_loss_grad", "cstar_nn_adam_step", "cstar_nn_train", "cstar_nn_attach"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -217,6 +235,89 @@ class Gauge:
         _check(lib().pfaffian_sign(self.h, _dp(m), len(m), ctypes.byref(o),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep)))
         return out, rep
+
+
+NN_PARAMS = 23040
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The learned preconditioner network (a cstar_nn handle); weights as in include/cstar.h."""
+
+    def __init__(self, weights=None):
+        h = ctypes.c_void_p()
+        if weights is None:
+            _check(lib().cstar_nn_create(None, ctypes.byref(h)))
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32)
+            if w.size != NN_PARAMS:
+                raise ValueError(f"expected {NN_PARAMS} weights")
+            _check(lib().cstar_nn_create(_fp(w), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().cstar_nn_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(NN_PARAMS, dtype=np.float32)
+        _check(lib().cstar_nn_get_weights(self.h, _fp(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != NN_PARAMS:
+            raise ValueError(f"expected {NN_PARAMS} weights")
+        _check(lib().cstar_nn_set_weights(self.h, _fp(w)))
+
+    def grad(self) -> np.ndarray:
+        g = np.zeros(NN_PARAMS)
+        _check(lib().cstar_nn_get_grad(self.h, _dp(g)))
+        return g
+
+    def zero_grad(self):
+        _check(lib().cstar_nn_zero_grad(self.h))
+
+    def apply(self, gauge: "Gauge", b, y, nvec=1):
+        _check(lib().cstar_nn_apply(self.h, gauge.h, int(nvec), _vp(b), _vp(y)))
+
+    def loss_grad(self, gauge: "Gauge", x, b, nvec=1, n_total=None) -> float:
+        loss = ctypes.c_double()
+        _check(lib().cstar_nn_loss_grad(self.h, gauge.h, int(nvec), _vp(x), _vp(b),
+                                        int(n_total if n_total else nvec), ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().cstar_nn_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def train(self, gauges, xs, nvec, m0, epochs, lr) -> np.ndarray:
+        n = len(gauges)
+        hs = (ctypes.c_void_p * n)(*[g.h.value for g in gauges])
+        ps = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        hist = np.zeros(epochs)
+        _check(lib().cstar_nn_train(self.h, hs, n, ps, int(nvec), float(m0), int(epochs), float(lr), _dp(hist)))
+        return hist
+
+    def attach(self, gauge: "Gauge"):
+        _check(lib().cstar_nn_attach(gauge.h, self.h))
+
+    @staticmethod
+    def detach(gauge: "Gauge"):
+        _check(lib().cstar_nn_attach(gauge.h, None))
 
 
 def sign_driver(provider, m_path, k, c, m_max):
