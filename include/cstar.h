@@ -228,9 +228,10 @@ cstar_status cstar_clover_norm_max(cstar_gauge *g, double *out);
  * V(x-mu,mu)^H psi(x-mu)) on the handle's x-doubled C* lattice with its FP32
  * links.  It is trained towards (Q^2)^-1, L = (1/N) sum_i |M(Q^2 x_i) - x_i|^2
  * / |x_i|^2, and used by q_lowest_eigs (opts.use_nn = 1 and a network
- * attached) on the Ritz block before every inner-precision Chebyshev filter
- * (the FP64 refinement filters the Ritz block itself), so that identity
- * weights reproduce the plain iteration; the plain solver answers if the
+ * attached): every iteration appends the preconditioned residuals
+ * M (A x_j - theta_j x_j) of the 2k lowest Ritz pairs of A = Q^2 to the
+ * Chebyshev-filtered block (the search space always contains the plain
+ * one; 2 * block + 2k <= 128).  The plain solver answers if the
  * preconditioned one fails (stats.nn_fallback).
  *
  * Weights: CSTAR_NN_PARAMS floats, layers in order, each [Cout][Cin][9][4][4]

@@ -34,11 +34,12 @@ namespace cstar {
 
 struct Workspace {
     int nb = 0;
+    int extra = 0;              // additional Y / T slots (preconditioned residuals)
     long n = 0;                 // complex entries per FP64 vector
-    double2 *XY = nullptr;      // 2nb vectors: X = [0,nb), Y = [nb,2nb)
-    double2 *AXY = nullptr;     // 2nb vectors: A X, A Y
-    double2 *T = nullptr;       // nb vectors
-    double2 *T2 = nullptr;      // nb vectors
+    double2 *XY = nullptr;      // 2nb + extra vectors: X = [0,nb), Y = [nb,2nb+extra)
+    double2 *AXY = nullptr;     // 2nb + extra vectors: A X, A Y
+    double2 *T = nullptr;       // nb + extra vectors
+    double2 *T2 = nullptr;      // nb + extra vectors
     float4 *F[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32 filter blocks (nb each)
     double2 *partial = nullptr;
     double2 *G = nullptr;       // device small matrix (up to 128 x 128)
@@ -58,15 +59,16 @@ void workspace_release(cstar_gauge *g) {
     g->ws = nullptr;
 }
 
-static cstar_status ws_get(cstar_gauge *g, int nb, Workspace **out) {
+static cstar_status ws_get(cstar_gauge *g, int nb, int extra, Workspace **out) {
     const long n = n_cplx(g->geo);
-    if (g->ws && g->ws->nb >= nb && g->ws->n == n) {
+    if (g->ws && g->ws->nb >= nb && g->ws->extra >= extra && g->ws->n == n) {
         *out = g->ws;
         return CSTAR_OK;
     }
     workspace_release(g);
     Workspace *w = new Workspace();
     w->nb = nb;
+    w->extra = extra;
     w->n = n;
     auto alloc = [&](size_t bytes, void **p) -> bool {
         if (hipMalloc(p, bytes) != hipSuccess) return false;
@@ -74,8 +76,8 @@ static cstar_status ws_get(cstar_gauge *g, int nb, Workspace **out) {
         return true;
     };
     const size_t v64 = (size_t)n * sizeof(double2), v32 = (size_t)n / 2 * sizeof(float4);
-    bool ok = alloc(2 * nb * v64, (void **)&w->XY) && alloc(2 * nb * v64, (void **)&w->AXY) &&
-              alloc(nb * v64, (void **)&w->T) && alloc(nb * v64, (void **)&w->T2) &&
+    bool ok = alloc((2 * nb + extra) * v64, (void **)&w->XY) && alloc((2 * nb + extra) * v64, (void **)&w->AXY) &&
+              alloc((nb + extra) * v64, (void **)&w->T) && alloc((nb + extra) * v64, (void **)&w->T2) &&
               alloc(gram_partial_bytes(), (void **)&w->partial) && alloc(128 * 128 * sizeof(double2), (void **)&w->G) &&
               alloc(128 * 128 * sizeof(double2), (void **)&w->C);
     for (int i = 0; i < 4 && ok; i++) ok = alloc(nb * v32, (void **)&w->F[i]);
@@ -99,11 +101,23 @@ struct Ctx {
     long ap64 = 0, ap_inner = 0, nn_applies = 0;
 };
 
-// Ritz block -> M X in FP32 through the attached network (in place on an FP32 block)
-cstar_status precondition32(Ctx &c, float4 *X32, int nv) {
-    cstar_status st = nn_apply_block(c.g, X32, nv);
+// Preconditioned residuals of the nr lowest Ritz pairs into R (FP64):
+//   R_j = M (A x_j - theta_j x_j),
+// with the attached network M ~ A^-1 applied in FP32.  For M close to A^-1 on
+// the modes above the wanted ones, M r_j approximates the error of x_j, so
+// these directions complement the Chebyshev-filtered block (a block
+// Davidson / LOBPCG-style correction).
+cstar_status precond_residuals(Ctx &c, const double2 *X, const double2 *AX, const double *theta, int nr, double2 *R) {
+    const long n = c.w->n;
+    CSTAR_HIP(hipMemcpyAsync(R, AX, sizeof(double2) * n * nr, hipMemcpyDeviceToDevice, c.s));
+    for (int j = 0; j < nr; j++)
+        CSTAR_HIP(launch_lincomb64(2 * n, -theta[j], (const double *)(X + j * n), 1.0, (double *)(R + j * n), 0.0,
+                                   nullptr, c.s));
+    CSTAR_HIP(launch_to_f32(c.g->geo, nr, R, c.w->F[0], c.s));
+    cstar_status st = nn_apply_block(c.g, c.w->F[0], nr);
     if (st) return st;
-    c.nn_applies += nv;
+    c.nn_applies += nr;
+    CSTAR_HIP(launch_to_f64(c.g->geo, nr, c.w->F[0], R, c.s));
     return CSTAR_OK;
 }
 
@@ -276,17 +290,13 @@ cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0
 // The same filter in an FP32 form on the F[] buffers: F[0] = X (converted),
 // the result converted back into Yout.
 cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2 *Yout, double a0, double acut,
-                      double bup, int deg, bool nn) {
+                      double bup, int deg) {
     Workspace *w = c.w;
     const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
     const double x0 = (a0 - cen) / e;
     double sig = 1.0 / x0;
     float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
     CSTAR_HIP(launch_to_f32(c.g->geo, nv, X, prev, c.s));
-    if (nn) {
-        cstar_status st = precondition32(c, prev, nv);
-        if (st) return st;
-    }
     CSTAR_HIP(q32(c, prec, prev, tq, nv));
     CSTAR_HIP(q32(c, prec, tq, cur, nv, sig / e, prev, -cen * sig / e));
     for (int j = 1; j < deg; j++) {
@@ -322,12 +332,14 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     if (nb > 64) return fail(CSTAR_EINVAL, "q_lowest_eigs: block must be <= 64");
     int deg = o.degree > 0 ? o.degree : 24;
     const int deg_max = std::max(deg, 800);
+    const bool use_nn = o.use_nn && g->nn;
+    const int nr = use_nn ? std::min(2 * k, nb) : 0;  // preconditioned residuals per iteration
+    if (use_nn && 2 * nb + nr > 128) return fail(CSTAR_EINVAL, "q_lowest_eigs: block too large for use_nn");
     Workspace *w = nullptr;
-    cstar_status st = ws_get(g, nb, &w);
+    cstar_status st = ws_get(g, nb, nr, &w);
     if (st) return st;
     Ctx c{g, w, g->stream, m0};
     const long n = w->n;
-    const bool use_nn = o.use_nn && g->nn;
     double2 *X = w->XY, *Y = w->XY + (long)nb * n;
     double2 *AX = w->AXY, *AY = w->AXY + (long)nb * n;
 
@@ -366,21 +378,26 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             // ---- filter: the whole block in the inner precisions; in FP64 only
             // the leading nq vectors (the guard vectors beyond the Q-reduced
             // subspace need no FP64 accuracy)
-            // (with the learned preconditioner M the inner-precision filter acts
-            // on M X; the FP64 refinement filters X itself)
             const int nf = fp64_filter ? nq : nb;
             if (fp64_filter) {
                 st = filter64(c, X, nf, Y, a0, acut, bup, deg, w->T, w->T2, AY);
             } else {
-                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg, use_nn);
+                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg);
             }
             if (st) return st;
+            // ---- learned preconditioner: append M r_j for the 2k wanted Ritz pairs
+            int nin = nf;
+            if (nr > 0) {
+                st = precond_residuals(c, X, AX, theta.data(), nr, Y + (long)nf * n);
+                if (st) return st;
+                nin = nf + nr;
+            }
             // ---- orthogonalise against X twice, then orthonormalise within
             for (int r = 0; r < 2; r++) {
-                st = project_out(c, X, nb, Y, nf);
+                st = project_out(c, X, nb, Y, nin);
                 if (st) return st;
             }
-            st = orthonormalise(c, Y, nf, w->T, &ny);
+            st = orthonormalise(c, Y, nin, w->T, &ny);
             if (st) return st;
             if (ny > 0) {
                 CSTAR_HIP(q64(c, Y, w->T, ny));
