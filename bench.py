@@ -27,6 +27,42 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# sources of the apply kernels; the committed counter summary records their hash
+APPLY_SOURCES = ("paper_2108_11989_amd/csrc/kernels_dirac.hip", "paper_2108_11989_amd/csrc/lattice_dev.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_traffic_32x32x32x32.md")
+
+
+def apply_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec_name: str, rhs_per_launch: float):
+    """HBM bytes per launch of the apply kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain
+    copy), interpolated linearly in the number of right-hand sides between the
+    measured launch widths; None if the summary is missing or was taken on
+    other kernel sources."""
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    src = [ln.split()[-1] for ln in lines if ln.startswith("source_sha256:")]
+    if not src or src[0] != apply_source_hash():
+        return None
+    pts = sorted((float(f[2]), float(f[3])) for f in (ln.split() for ln in lines if ln.startswith("traffic "))
+                 if f[1] == prec_name)
+    if len(pts) < 2:
+        return None
+    (n0, b0), (n1, b1) = pts[0], pts[-1]
+    return b0 + (b1 - b0) * (rhs_per_launch - n0) / (n1 - n0)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -66,6 +102,81 @@ def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
     dt = time.time() - t0
     return {"value": n / dt, "unit": "Dirac applies/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3 (clover setup {t_setup:.1f} s not counted)"}
+
+
+def train_network(args, w, q, m_train):
+    """The learned preconditioner, trained here on the GPU (library kernels) on
+    smoothed 8^4 fields of the workload's distribution (the network is local:
+    its weights do not depend on the lattice size)."""
+    from paper_2108_11989_amd import cstar, learned, synth
+    t0 = time.perf_counter()
+    gs, xs = [], []
+    for i in range(args.train_fields):
+        s3, t3 = synth.make_field(8, 8, w["eps"], 5000 + i, smear_steps=w["smear"])
+        g = cstar.Gauge(s3, t3, q, synth.CSW_SU3, synth.CSW_U1)
+        gs.append(g)
+        xs.append(learned.training_vectors(g, m_train, 4, 4, seed=7000 + 10 * i))
+    t_data = time.perf_counter() - t0
+    net, hist = learned.train(gs, xs, 8, m_train, args.train_epochs, 1e-3)
+    for g in gs:
+        g.close()
+    info = {"fields": args.train_fields, "lattice": "8x8^3", "epochs": args.train_epochs, "pairs_per_field": 8,
+            "loss_first": float(hist[0]), "loss_last": float(hist[-1]), "s_data": t_data,
+            "s_train": time.perf_counter() - t0 - t_data}
+    log(f"[bench] network trained: loss {hist[0]:.4f} -> {hist[-1]:.4f} ({info['s_train']:.1f} s)")
+    return net, info
+
+
+FORMS = (("plain_fp64", "fp64", 0), ("plain_mixed", "bf16", 0), ("learned_mixed", "bf16", 1))
+
+
+def compare_forms(args, net, su3_d, th_d, q, masses, full_path):
+    """Plain FP64, plain mixed precision and learned + mixed precision: seconds
+    and applies per eigensolve at the given masses (cold start), or per
+    Pfaffian sign over the whole path."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    inner = {"bf16": cstar.FP32_BF16LINKS, "fp64": cstar.FP64}
+    res = {}
+    for name, prec, use_nn in FORMS:
+        g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+        if use_nn:
+            net.attach(g)
+        opts = cstar.eig_opts(inner=inner[prec], tol=args.tol, max_iter=1000, use_nn=use_nn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if full_path:
+            signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
+            r = {"s_per_sign": time.perf_counter() - t0, "applies": rep.applies, "nn_applies": rep.nn_applies,
+                 "fallbacks": rep.nn_fallbacks, "points_solved": rep.n_points,
+                 "signs": "".join("+" if v > 0 else "-" for v in signs)}
+        else:
+            r = {"solves": []}
+            for m in masses:
+                t1 = time.perf_counter()
+                ev, res_, st = g.lowest_eigs(float(m), args.k, opts)
+                r["solves"].append({"m0": float(m), "s": time.perf_counter() - t1, "iterations": st.iterations,
+                                    "applies_inner": st.applies_inner, "applies_fp64": st.applies_fp64,
+                                    "nn_applies": st.nn_applies, "fallback": st.nn_fallback,
+                                    "lambda": [float(x) for x in ev], "resid_max": float(np.max(res_))})
+            r["s"] = time.perf_counter() - t0
+        if use_nn:
+            cstar.Net.detach(g)
+        g.close()
+        res[name] = r
+        log(f"[bench] {name}: {json.dumps(r)[:300]}")
+    if full_path:
+        res["signs_agree"] = len({res[n]["signs"] for n, _, _ in FORMS}) == 1
+    else:
+        # the plain FP64 solve judges the others: |lambda - lambda_fp64| within the residual bounds
+        ref = res["plain_fp64"]["solves"]
+        res["eigenvalues_agree"] = all(
+            abs(a - b) <= sa["resid_max"] + sb["resid_max"] + 1e-12
+            for n in ("plain_mixed", "learned_mixed")
+            for sa, sb in zip(res[n]["solves"], ref) for a, b in zip(sa["lambda"], sb["lambda"]))
+    return res
 
 
 def kernel_probe(args, su3_d, th_d, q, T, L):
@@ -114,9 +225,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="batched_32^4")
-    ap.add_argument("--k", type=int, default=3, help="eigenvalues (Kramers pairs) per mass point")
+    ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--path-points", type=int, default=0, help="use only the first n kappas (0 = all)")
@@ -127,6 +238,12 @@ def main():
     ap.add_argument("--probe-nrhs", type=int, default=0, help="multi-RHS width of the probe (0: the solver block)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run one device copy of this many GiB (counter calibration)")
+    ap.add_argument("--compare-masses", type=int, default=1,
+                    help="learned vs plain: cold eigensolves at the first n path masses after the timed region (0: skip)")
+    ap.add_argument("--compare-path", action="store_true",
+                    help="learned vs plain over the whole path (three Pfaffian signs; minutes), instead of the timed step")
+    ap.add_argument("--train-fields", type=int, default=8)
+    ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -144,7 +261,7 @@ def main():
         log("no GPU")
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
-    T, L, q = w["T"], w["L"], w["q"][0]
+    T, L, q = w["T"], w["L"], w["q"][0]  # q: the first charge (comparisons, probes, CPU baseline)
     log(f"[bench] workload {args.workload}: {T}x{L}^3, eps {w['eps']}, seed {w['seed']}, smear {w['smear']}")
     t0 = time.time()
     su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
@@ -160,30 +277,45 @@ def main():
     opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000)
     nsites2 = 2 * T * L ** 3
 
+    if args.compare_path:
+        net, info = train_network(args, w, q, float(masses[0]))
+        res = compare_forms(args, net, su3_d, th_d, q, masses, True)
+        net.close()
+        print(json.dumps({"learned_vs_plain_path": res, "train": info, "workload": args.workload,
+                          "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol}), flush=True)
+        return
+
+    charges = [float(x) for x in w["q"]]
+
     def step():
-        g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
-        g.timing(True)
-        signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
-        tm = g.read_timing()
-        g.close()
-        return signs, rep, tm
+        """One Pfaffian sign over the whole path for every quark charge of the workload."""
+        out = []
+        for qc in charges:
+            g = cstar.Gauge(su3_d, th_d, qc, synth.CSW_SU3, synth.CSW_U1)
+            g.timing(True)
+            signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
+            out.append((signs, rep, g.read_timing()))
+            g.close()
+            log(f"[bench]   q = {qc:+.4f}: {rep.n_points} mass points, {rep.applies} applies, "
+                f"crossings {rep.n_crossings}, signs {''.join('+' if v > 0 else '-' for v in signs)}")
+        return out
 
     for i in range(args.warmup):
         t0 = time.time()
-        signs, rep, _ = step()
-        log(f"[bench] warmup {i}: {time.time() - t0:.2f} s, {rep.n_points} mass points, {rep.applies} applies")
+        step()
+        log(f"[bench] warmup {i}: {time.time() - t0:.2f} s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     applies = 0
     tms = []
     for i in range(args.steps):
-        signs, rep, tm = step()
-        applies += rep.applies
-        tms.append(tm)
-        log(f"[bench] step {i}: {rep.n_points} points, {rep.applies} applies, crossings {rep.n_crossings}")
+        res = step()
+        for signs, rep, tm in res:
+            applies += rep.applies
+            tms.append(tm)
+        log(f"[bench] step {i} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    log(f"[bench] signs over the path: {''.join('+' if s > 0 else '-' for s in signs)}")
 
     # dominant kernel: the precision with the most kernel time
     ms = [sum(t[p]["ms"] for t in tms) for p in range(3)]
@@ -196,6 +328,13 @@ def main():
     kern_name = {0: "apply FP64", 1: "apply FP32", 2: "apply FP32/BF16-links"}[dom]
     log(f"[bench] kernel time by precision (ms): {ms}; dominant {kern_name}: {launches} launches, "
         f"{rhs} rhs, avg {ms[dom] / max(launches, 1):.3f} ms/launch, {achieved:.0f} GB/s")
+
+    compare = None
+    if args.compare_masses > 0:
+        net, info = train_network(args, w, q, float(masses[0]))
+        compare = {"train": info, "forms": compare_forms(args, net, su3_d, th_d, q, masses[:args.compare_masses],
+                                                         False)}
+        net.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -217,12 +356,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": f"{T}x{L}^3", "sites_doubled": nsites2,
                    "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol,
-                   "inner": args.inner, "s_per_sign": dt / args.steps,
-                   "mass_points_solved": rep.n_points, "crossings": rep.n_crossings},
+                   "inner": args.inner, "charges": charges, "s_per_sign": dt / args.steps / len(charges),
+                   "mass_points_solved": [r.n_points for _, r, _ in res],
+                   "crossings": [r.n_crossings for _, r, _ in res],
+                   "signs": ["".join("+" if v > 0 else "-" for v in sg) for sg, _, _ in res]},
         "roofline": {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic({0: "fp64", 1: "fp32", 2: "bf16"}[dom], rhs / max(launches, 1)),
+                     "algorithmic_bytes_per_launch": byts / max(launches, 1),
                      "avg_launch_ms": ms[dom] / max(launches, 1), "rhs_per_launch": rhs / max(launches, 1)},
         "cpu_baseline": cpu,
+        "learned_vs_plain": compare,
     }
     print(json.dumps(out), flush=True)
 

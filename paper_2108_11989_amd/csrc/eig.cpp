@@ -8,12 +8,14 @@
 // orthogonal eigenvectors with the same eigenvalue), so k eigenvalues counted
 // once per pair need a block of at least 2k vectors.  Each iteration:
 //   Y = p_d(A) X        Chebyshev filter of degree d damping [a_cut, b_up]
-//                       (inner precision: FP32 with FP32 or BF16 links, or FP64)
 //   Y <- orth(Y - X X^H Y)                       FP64, SVQB orthonormalisation
 //   [X Y] Rayleigh-Ritz with A in FP64 (A applied in FP64) -> keep nb lowest
 //   Rayleigh-Ritz of Q on X -> signed lambda, residuals ||Q z - lambda z||
-// Mixed precision: the filter runs in the inner precision until the wanted
-// residuals reach its noise floor, then in FP64 (refinement).
+// Plain FP64 form: the filter in FP64.  Mixed forms: the filter acts on the
+// deflated block p(A) X - X p(Theta) (same span with X), driven by the FP64
+// residuals, in FP32 arithmetic with BF16 (then FP32) links; its rounding is
+// relative to the residuals, so the iteration converges to FP64 accuracy
+// without FP64 filtering.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +34,8 @@
 
 namespace cstar {
 
+constexpr int kMaxDegree = 800;  // largest Chebyshev degree of one filter
+
 struct Workspace {
     int nb = 0;
     int extra = 0;              // additional Y / T slots (preconditioned residuals)
@@ -40,7 +44,9 @@ struct Workspace {
     double2 *AXY = nullptr;     // 2nb + extra vectors: A X, A Y
     double2 *T = nullptr;       // nb + extra vectors
     double2 *T2 = nullptr;      // nb + extra vectors
-    float4 *F[4] = {nullptr, nullptr, nullptr, nullptr};  // FP32 filter blocks (nb each)
+    float4 *F[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // FP32 filter blocks (nb each)
+    float *coef = nullptr;              // per-vector recurrence coefficients [kMaxDegree][nb] (device)
+    std::vector<float> coef_host;       // their host staging copy (alive until the copy completes)
     double2 *partial = nullptr;
     double2 *G = nullptr;       // device small matrix (up to 128 x 128)
     double2 *C = nullptr;
@@ -80,7 +86,8 @@ static cstar_status ws_get(cstar_gauge *g, int nb, int extra, Workspace **out) {
               alloc((nb + extra) * v64, (void **)&w->T) && alloc((nb + extra) * v64, (void **)&w->T2) &&
               alloc(gram_partial_bytes(), (void **)&w->partial) && alloc(128 * 128 * sizeof(double2), (void **)&w->G) &&
               alloc(128 * 128 * sizeof(double2), (void **)&w->C);
-    for (int i = 0; i < 4 && ok; i++) ok = alloc(nb * v32, (void **)&w->F[i]);
+    for (int i = 0; i < 5 && ok; i++) ok = alloc(nb * v32, (void **)&w->F[i]);
+    ok = ok && alloc(sizeof(float) * kMaxDegree * nb, (void **)&w->coef);
     if (!ok) {
         (void)hipGetLastError();
         ws_free(w);
@@ -134,13 +141,16 @@ hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv, double ea = 1.0,
     return handle_apply(c.g, CSTAR_FP64, a);
 }
 hipError_t q32(Ctx &c, cstar_prec prec, const float4 *in, float4 *out, int nv, double ea = 1.0,
-               const float4 *y = nullptr, double eb = 0.0, const float4 *z = nullptr, double ec = 0.0) {
+               const float4 *y = nullptr, double eb = 0.0, const float4 *z = nullptr, double ec = 0.0,
+               const float4 *w = nullptr, const float *ew = nullptr) {
     ApplyArgs a{in, out, (long)c.w->n / 2 * (long)sizeof(float4), nv, 1, nullptr, c.m};
     a.y = y;
     a.z = z;
     a.ea = ea;
     a.eb = eb;
     a.ec = ec;
+    a.w = w;
+    a.ew = ew;
     c.ap_inner += nv;
     return handle_apply(c.g, prec, a);
 }
@@ -287,29 +297,66 @@ cstar_status filter64(Ctx &c, const double2 *X, int nv, double2 *Yout, double a0
     return CSTAR_OK;
 }
 
-// The same filter in an FP32 form on the F[] buffers: F[0] = X (converted),
-// the result converted back into Yout.
-cstar_status filter32(Ctx &c, cstar_prec prec, const double2 *X, int nv, double2 *Yout, double a0, double acut,
-                      double bup, int deg) {
+// Deflated form of the filter for Ritz vectors X (X^H A X = diag(theta),
+// X^H X = 1) with residuals R = A X - X diag(theta) (FP64).  It computes
+//   Z = p(A) X - X p(diag(theta)),   p(t) = T_d(x(t)) / T_d(x(a0)),
+// whose span with X equals that of [X, p(A) X].  With tau_j(m) the scalar
+// recurrence at theta_m (tau_0 = 1, tau_1 = sigma_1 x(theta_m)), the
+// normalised Z_j obeys
+//   Z_1 = sigma_1/e R,
+//   Z_{j+1} = 2 sigma_{j+1}/e (A - cen) Z_j - sigma_j sigma_{j+1} Z_{j-1} + 2 sigma_{j+1}/e R diag(tau_j),
+// so the operator is only applied to Z, which is of the size of the
+// residual: its rounding (FP32 arithmetic, FP32 or BF16 links) is relative to
+// the residual and sets no floor on the attainable accuracy, unlike
+// filtering X itself.  Buffers: F[0..3] rotate, F[4] holds R in FP32.
+cstar_status filter_deflated(Ctx &c, cstar_prec prec, const double2 *X, const double2 *AX, const double *theta,
+                             int nv, double2 *Yout, double a0, double acut, double bup, int deg, double2 *Rtmp) {
     Workspace *w = c.w;
+    const long n = w->n;
     const double e = 0.5 * (bup - acut), cen = 0.5 * (bup + acut);
     const double x0 = (a0 - cen) / e;
-    double sig = 1.0 / x0;
-    float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
-    CSTAR_HIP(launch_to_f32(c.g->geo, nv, X, prev, c.s));
-    CSTAR_HIP(q32(c, prec, prev, tq, nv));
-    CSTAR_HIP(q32(c, prec, tq, cur, nv, sig / e, prev, -cen * sig / e));
+    deg = std::max(1, std::min(deg, kMaxDegree));
+    // R = A X - X diag(theta) in FP64, then FP32
+    CSTAR_HIP(hipMemcpyAsync(Rtmp, AX, sizeof(double2) * n * nv, hipMemcpyDeviceToDevice, c.s));
+    for (int m = 0; m < nv; m++)
+        CSTAR_HIP(launch_lincomb64(2 * n, -theta[m], (const double *)(X + m * n), 1.0, (double *)(Rtmp + m * n), 0.0,
+                                   nullptr, c.s));
+    float4 *Rf = w->F[4];
+    CSTAR_HIP(launch_to_f32(c.g->geo, nv, Rtmp, Rf, c.s));
+    // scalar recurrences: sigma_j and tau_j(m); coefficients of R for steps j -> j+1
+    std::vector<double> sig(deg + 1);
+    sig[1] = 1.0 / x0;
+    for (int j = 1; j < deg; j++) sig[j + 1] = 1.0 / (2.0 * x0 - sig[j]);
+    std::vector<double> tprev(nv, 1.0), tcur(nv);
+    for (int m = 0; m < nv; m++) tcur[m] = sig[1] * (theta[m] - cen) / e;
+    w->coef_host.assign((size_t)deg * w->nb, 0.f);
     for (int j = 1; j < deg; j++) {
-        const double sig2 = 1.0 / (2.0 * x0 - sig);
+        for (int m = 0; m < nv; m++) {
+            w->coef_host[(size_t)j * w->nb + m] = (float)(2.0 * sig[j + 1] / e * tcur[m]);
+            const double tn = 2.0 * sig[j + 1] * (theta[m] - cen) / e * tcur[m] - sig[j] * sig[j + 1] * tprev[m];
+            tprev[m] = tcur[m];
+            tcur[m] = tn;
+        }
+    }
+    CSTAR_HIP(hipMemcpyAsync(w->coef, w->coef_host.data(), sizeof(float) * w->coef_host.size(),
+                             hipMemcpyHostToDevice, c.s));
+    float4 *prev = w->F[0], *cur = w->F[1], *nxt = w->F[2], *tq = w->F[3];
+    const size_t vb = (size_t)n / 2 * sizeof(float4) * nv;
+    CSTAR_HIP(hipMemsetAsync(prev, 0, vb, c.s));  // Z_0 = 0
+    CSTAR_HIP(hipMemsetAsync(cur, 0, vb, c.s));
+    CSTAR_HIP(launch_lincomb32(2 * n * nv, (float)(sig[1] / e), (const float *)Rf, 0.f, (float *)cur, 0.f, nullptr,
+                               c.s));
+    for (int j = 1; j < deg; j++) {
+        const double a = 2.0 * sig[j + 1] / e;
         CSTAR_HIP(q32(c, prec, cur, tq, nv));
-        CSTAR_HIP(q32(c, prec, tq, nxt, nv, 2.0 * sig2 / e, cur, -2.0 * sig2 * cen / e, prev, -sig * sig2));
+        CSTAR_HIP(q32(c, prec, tq, nxt, nv, a, cur, -a * cen, prev, -sig[j] * sig[j + 1], Rf, w->coef + (size_t)j * w->nb));
         float4 *t = prev;
         prev = cur;
         cur = nxt;
         nxt = t;
-        sig = sig2;
     }
     CSTAR_HIP(launch_to_f64(c.g->geo, nv, cur, Yout, c.s));
+    CSTAR_HIP(hipStreamSynchronize(c.s));  // the coefficient staging copy must finish before it is reused
     return CSTAR_OK;
 }
 
@@ -366,6 +413,7 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     const char *venv = getenv("CSTAR_VERBOSE");
     const bool verbose = venv && venv[0] == '1';
     bool fp64_filter = (inner == CSTAR_FP64);
+    bool refine = false;  // wanted pairs resolved: filter the leading nq vectors only
     double last_rabs = 1e300;
     int stall = 0;
     int nq = nb;  // size of the Q-reduced leading subspace (set after each RR)
@@ -375,14 +423,17 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     for (it = 0; it < o.max_iter; it++) {
         int ny = 0;
         if (have_ritz) {
-            // ---- filter: the whole block in the inner precisions; in FP64 only
-            // the leading nq vectors (the guard vectors beyond the Q-reduced
-            // subspace need no FP64 accuracy)
-            const int nf = fp64_filter ? nq : nb;
+            // ---- filter.  Plain FP64 form: p(A) X in FP64.  Mixed forms: the
+            // deflated filter in FP32 arithmetic (BF16, then FP32 links), whose
+            // rounding is relative to the residual.  The whole block is
+            // filtered until the wanted pairs are resolved, then only the
+            // leading nq vectors (the guard vectors beyond the Q-reduced
+            // subspace only bound the cut).
+            const int nf = refine ? nq : nb;
             if (fp64_filter) {
                 st = filter64(c, X, nf, Y, a0, acut, bup, deg, w->T, w->T2, AY);
             } else {
-                st = filter32(c, inner, X, nf, Y, a0, acut, bup, deg);
+                st = filter_deflated(c, inner, X, AX, theta.data(), nf, Y, a0, acut, bup, deg, w->T2);
             }
             if (st) return st;
             // ---- learned preconditioner: append M r_j for the 2k wanted Ritz pairs
@@ -551,24 +602,21 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             it++;
             break;
         }
-        // precision ladder: the filter runs in BF16-link, then FP32-link, then
-        // FP64 arithmetic; each level generates search directions until the
-        // wanted residuals reach its noise floor (the level's operator differs
-        // from the FP64 one by ~2^-8 relative for BF16 links, ~2^-23 for FP32),
-        // or stop improving for three iterations.
+        // precision ladder of the mixed forms: the deflated filter has no
+        // accuracy floor, so it stays with BF16 links while the wanted
+        // residuals keep falling; after three iterations without progress it
+        // moves to FP32 links, and after three more to the FP64 filter.
         double rabs = 0.0;
         for (int i = 0; i < k && i < (int)prs.size(); i++) rabs = std::max(rabs, prs[i].err);
         if ((int)prs.size() < k) rabs = 1e300;
         stall = (rabs > 0.8 * last_rabs) ? stall + 1 : 0;
-        if (!fp64_filter) {
-            const double floor_inner = (inner == CSTAR_FP32_BF16LINKS ? 4e-3 : 5e-9) * qscale;
-            if (rabs < 20.0 * floor_inner || stall >= 3) {
-                if (inner == CSTAR_FP32_BF16LINKS)
-                    inner = CSTAR_FP32;
-                else
-                    fp64_filter = true;
-                stall = 0;
-            }
+        if (rmax < 1e-4) refine = true;
+        if (!fp64_filter && stall >= 3) {
+            if (inner == CSTAR_FP32_BF16LINKS)
+                inner = CSTAR_FP32;
+            else
+                fp64_filter = true;
+            stall = 0;
         }
         // filter degree: about two e-folds of damping per iteration between the
         // slowest wanted Ritz value and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up),

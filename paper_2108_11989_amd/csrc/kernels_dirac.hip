@@ -222,16 +222,44 @@ __device__ __forceinline__ void pin(cx<R> acc[12]) {
     for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
 }
 
-// Epilogue of a launch: out = a * ([g5] D psi) + b * y + c * z, with y and z
-// spinor blocks of the output's layout (used by the Chebyshev recurrence to
-// form its three-term update without another pass over memory).
+// Epilogue of a launch: out = a * ([g5] D psi) + b * y + c * z + e_j * w, with
+// y, z, w spinor blocks of the output's layout and e_j a coefficient per
+// right-hand side (used by the Chebyshev recurrences to form their update
+// without another pass over memory).
 template <class V>
 struct Epi {
     const V *y, *z;
     float a, b, c;      // FP32 forms
     double ad, bd, cd;  // FP64 form
     int on;
+    const V *w;         // optional fourth operand (null: none)
+    const void *ew;     // its coefficients: float [nrhs] (FP32 forms) or double [nrhs] (FP64)
 };
+
+template <class R, class V>
+__device__ __forceinline__ void apply_epilogue(const Geo &g, const Epi<V> &ep, int j, long joff, int p, int h, int c,
+                                               cx<R> acc[12]) {
+    if (!ep.on) return;
+    // one operand live at a time
+    const R a = sizeof(R) == 8 ? R(ep.ad) : R(ep.a);
+    const R b = sizeof(R) == 8 ? R(ep.bd) : R(ep.b);
+    const R cc = sizeof(R) == 8 ? R(ep.cd) : R(ep.c);
+    cx<R> w[12];
+    SpinorIO<R>::load(ep.y + joff, g, p, h, c, w);
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {fma(b, w[k].re, a * acc[k].re), fma(b, w[k].im, a * acc[k].im)};
+    pin(acc);
+    SpinorIO<R>::load(ep.z + joff, g, p, h, c, w);
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {fma(cc, w[k].re, acc[k].re), fma(cc, w[k].im, acc[k].im)};
+    if (ep.w) {
+        pin(acc);
+        const R e = reinterpret_cast<const R *>(ep.ew)[j];
+        SpinorIO<R>::load(ep.w + joff, g, p, h, c, w);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = {fma(e, w[k].re, acc[k].re), fma(e, w[k].im, acc[k].im)};
+    }
+}
 
 // One site of the x-doubled lattice (lane = pair x copy), one right-hand side:
 // out = (4+m) chi + SW chi - 1/2 (hopping sum), optionally times g5.
@@ -239,7 +267,7 @@ template <class Fmt, int LOG2L>
 __device__ __forceinline__ void site_apply(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
                                            typename Prec<Fmt>::V *__restrict__ out, int p, int h, int c, int t, int x1,
                                            int x2, int x3, double mass, int gamma5,
-                                           const Epi<typename Prec<Fmt>::V> &ep, long joff) {
+                                           const Epi<typename Prec<Fmt>::V> &ep, int j, long joff) {
     using R = typename Prec<Fmt>::R;
     cx<R> acc[12];
 #pragma unroll
@@ -270,18 +298,7 @@ __device__ __forceinline__ void site_apply(const Geo &g, const GaugeDev &d, cons
         if (k >= 6) o = scale(o, s5);
         acc[k] = o;
     }
-    if (ep.on) {
-        cx<R> yv[12], zv[12];
-        SpinorIO<R>::load(ep.y + joff, g, p, h, c, yv);
-        SpinorIO<R>::load(ep.z + joff, g, p, h, c, zv);
-        const R a = sizeof(R) == 8 ? R(ep.ad) : R(ep.a);
-        const R b = sizeof(R) == 8 ? R(ep.bd) : R(ep.b);
-        const R cc = sizeof(R) == 8 ? R(ep.cd) : R(ep.c);
-#pragma unroll
-        for (int k = 0; k < 12; k++)
-            acc[k] = {fma(cc, zv[k].re, fma(b, yv[k].re, a * acc[k].re)),
-                      fma(cc, zv[k].im, fma(b, yv[k].im, a * acc[k].im))};
-    }
+    apply_epilogue<R, typename Prec<Fmt>::V>(g, ep, j, joff, p, h, c, acc);
     SpinorIO<R>::store(out, g, p, h, c, acc);
 }
 
@@ -359,7 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::w
     if (tile >= ntiles) return;
     int p, h, c, t, x1, x2, x3;
     if (!tile_site<LOG2L>(g, tile, threadIdx.x, p, h, c, t, x1, x2, x3)) return;
-    site_apply<Fmt, LOG2L>(g, d, in, out, p, h, c, t, x1, x2, x3, mass, gamma5, ep, 0);
+    site_apply<Fmt, LOG2L>(g, d, in, out, p, h, c, t, x1, x2, x3, mass, gamma5, ep, 0, 0);
 }
 
 // Time-column form (L = 2^LOG2L): a lane owns one spatial site (one copy)
@@ -401,7 +418,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::w
         // slice rather than held (and spilled) across the loop
         int cj_ = c, x1j = x1, x2j = x2, x3j = x3;
         asm volatile("" : "+v"(cj_), "+v"(x1j), "+v"(x2j), "+v"(x3j));
-        site_apply<Fmt, LOG2L>(g, d, inj, outj, p, h, cj_, t, x1j, x2j, x3j, m, gamma5, ep, j * stride);
+        site_apply<Fmt, LOG2L>(g, d, inj, outj, p, h, cj_, t, x1j, x2j, x3j, m, gamma5, ep, j, j * stride);
     }
 }
 
@@ -427,17 +444,168 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<Fmt>::w
         int pj = p, hj = h, cj_ = c, tj = t, x1j = x1, x2j = x2, x3j = x3;
         asm volatile("" : "+v"(pj), "+v"(hj), "+v"(cj_), "+v"(tj), "+v"(x1j), "+v"(x2j), "+v"(x3j));
         site_apply<Fmt, LOG2L>(g, dj, in + j * stride, out + j * stride, pj, hj, cj_, tj, x1j, x2j, x3j, m, gamma5, ep,
-                               j * stride);
+                               j, j * stride);
     }
 }
+
+// Time-marching form (L = 2^LOG2L >= 8).  A workgroup owns RX1 x RX2 rows
+// (x1, x2) of the spatial lattice -- a row is the L sites of x3 times the two
+// copies, 2L lanes -- and one segment of TB time slices, which it walks in
+// order.  Every iteration loads one slice: the x3 neighbours lie in the same
+// wave and the x1 / x2 neighbours in sibling waves that load the same lines at
+// the same time, so they come from L1 / L2 instead of HBM.  The time hops are
+// carried in registers: iteration s loads psi(s) and the link V(s-1, 0) once,
+// completes site s-1 with its forward time hop and starts site s with its
+// backward time hop (from the projected psi(s-1) kept from the last iteration).
+// The running sum is -2 (SW + 4 + m) psi + hops, so the result is -1/2 of it.
+template <class R, class V>
+__device__ __forceinline__ void finish_site(const Geo &g, V *__restrict__ out, const Epi<V> &ep, int j, long joff, int p,
+                                            int h, int c, int gamma5, cx<R> acc[12]) {
+    const R s5 = gamma5 ? R(-1) : R(1);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        acc[k] = scale(acc[k], R(-0.5));
+        if (k >= 6) acc[k] = scale(acc[k], s5);
+    }
+    apply_epilogue<R, V>(g, ep, j, joff, p, h, c, acc);
+    SpinorIO<R>::store(out, g, p, h, c, acc);
+}
+
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB>
+__global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
+    Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
+    long stride, int nrhs, int gamma5, const double *__restrict__ masses, double mass0,
+    Epi<typename Prec<Fmt>::V> ep) {
+    using R = typename Prec<Fmt>::R;
+    using V = typename Prec<Fmt>::V;
+    constexpr int L = 1 << LOG2L;
+    constexpr int N1 = L / RX1, N2 = L / RX2;
+    const int nseg = (g.T + TB - 1) / TB;
+    const int per_rhs = N1 * N2 * nseg;
+    const int item = xcd_tile(gridDim.x);
+    const int j = item / per_rhs;
+    if (j >= nrhs) return;
+    int r = item - j * per_rhs;
+    const int tile2 = r % N2;
+    r /= N2;
+    const int tile1 = r % N1;
+    const int seg = r / N1;
+    const int lane = threadIdx.x;
+    const int c = lane & 1;
+    const int x3 = (lane >> 1) & (L - 1);
+    const int row = lane >> (LOG2L + 1);
+    const int x2 = tile2 * RX2 + row % RX2;
+    const int x1 = tile1 * RX1 + row / RX2;
+    const int t0 = seg * TB;
+    const int t1 = min(t0 + TB, g.T);
+    const double mass = masses ? masses[j] : mass0;
+    const R dm = R(4.0 + mass);
+    const typename Prec<Fmt>::V *inj = in + j * stride;
+    typename Prec<Fmt>::V *outj = out + j * stride;
+    const long joff = j * stride;
+    const int xs = x1 + x2 + x3;
+    const R tsign = g.time_bc < 0 ? R(-1) : R(1);
+    const R csg = c ? R(-1) : R(1);
+
+    // prologue: projected psi(t0 - 1) for the backward time hop into t0
+    cx<R> hb[6];
+    {
+        const int tp = t0 == 0 ? g.T - 1 : t0 - 1;
+        cx<R> v[12];
+        SpinorIO<R>::load(inj, g, (tp + xs) & 1, pair_index<LOG2L>(g, tp, x1, x2, x3), c, v);
+        project<0, 1>(v, hb);
+        if (t0 == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) hb[k] = scale(hb[k], tsign);
+        }
+    }
+    cx<R> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {R(0), R(0)};
+#pragma nounroll
+    for (int s = t0; s <= t1; s++) {
+        const int ts = s == g.T ? 0 : s;
+        const int tm = s == 0 ? g.T - 1 : s - 1;
+        const int ps = (ts + xs) & 1, pm = (tm + xs) & 1;
+        const int hs = pair_index<LOG2L>(g, ts, x1, x2, x3), hm = pair_index<LOG2L>(g, tm, x1, x2, x3);
+        cx<R> v[12];
+        SpinorIO<R>::load(inj, g, ps, hs, c, v);
+        Link<R> Lt;  // V(s-1, 0) at the lane's spatial site
+        Fmt::load(d, g, pm, 0, hm, csg, Lt);
+        if (s > t0) {
+            // forward time hop of site s-1: (1 - g0) V(s-1,0) psi(s); then site s-1 is complete
+            cx<R> hf[6], gf[6];
+            project<0, -1>(v, hf);
+            if (s == g.T) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) hf[k] = scale(hf[k], tsign);
+            }
+            link_mul<Fmt, false>(Lt, hf, gf);
+            accumulate<0, -1>(acc, gf);
+            finish_site<R, V>(g, outj, ep, j, joff, pm, hm, c, gamma5, acc);
+        }
+        if (s < t1) {
+            // site s: backward time hop (scaled by -1/2 so that the final -2
+            // restores it), local term, then the spatial hops
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[k] = {R(0), R(0)};
+            {
+                cx<R> gb[6];
+                link_mul<Fmt, true>(Lt, hb, gb);
+                accumulate<0, 1>(acc, gb);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[k] = scale(acc[k], R(-0.5));
+            pin(acc);
+            clover_add<R>(d, g, ps, hs, c, v, acc);
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[k] = scale(acc[k] + scale(v[k], dm), R(-2));
+            project<0, 1>(v, hb);
+            pin(acc);
+            // opaque coordinates: recomputed per slice rather than held across the loop
+            int cj_ = c, x1j = x1, x2j = x2, x3j = x3;
+            asm volatile("" : "+v"(cj_), "+v"(x1j), "+v"(x2j), "+v"(x3j));
+            hop_pair<Fmt, 1, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            pin(acc);
+            hop_pair<Fmt, 2, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            pin(acc);
+            hop_pair<Fmt, 3, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            pin(acc);
+        }
+    }
+}
+
+// rows of a marching workgroup: 1024 lanes for the FP32 forms, 512 for FP64
+template <class Fmt>
+struct March {
+    static constexpr int lanes = 1024;
+};
+template <>
+struct March<FmtF64> {
+    static constexpr int lanes = 512;
+};
+constexpr int march_rows(int lanes, int log2l) { return lanes >> (log2l + 1); }
+constexpr int march_rx1(int rows) { return rows >= 64 ? 8 : rows >= 16 ? 4 : 2; }
 
 template <class Fmt, int LOG2L>
 static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
     using V = typename Prec<Fmt>::V;
     Epi<V> ep{(const V *)a.y, (const V *)(a.z ? a.z : a.y), (float)a.ea, (float)a.eb, (float)(a.z ? a.ec : 0.0),
-              a.ea, a.eb, a.z ? a.ec : 0.0, a.y ? 1 : 0};
+              a.ea, a.eb, a.z ? a.ec : 0.0, a.y ? 1 : 0, (const V *)(a.y ? a.w : nullptr), a.ew};
     const long st = a.stride / (long)sizeof(V);
     const int ntiles = (4 * g.Vh + 255) / 256;
+    if constexpr (LOG2L >= 3) {
+        constexpr int rows = march_rows(March<Fmt>::lanes, LOG2L);
+        constexpr int RX1 = march_rx1(rows), RX2 = rows / RX1;
+        constexpr int TB = 8;
+        static_assert(RX1 * RX2 * (2 << LOG2L) == March<Fmt>::lanes, "march tile");
+        const int nseg = (g.T + TB - 1) / TB;
+        const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * a.nrhs;
+        const int nwg = (int)((items + 7) / 8 * 8);
+        hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB>), dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d,
+                           (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
+        return;
+    }
     if constexpr (LOG2L >= 2) {
         // lanes per right-hand side: 2 L^3 (sites x copies) x T / TC
         const long lanes = 2L * (1L << (3 * LOG2L)) * (g.T % 4 == 0 ? g.T / 4 : g.T / 2);

@@ -27,6 +27,9 @@ CASES = [
     (4, 4, 1.0, 7, 2 / 3, -1),
     (8, 6, 0.3, 11, 2 / 3, 1),
     (2, 2, 0.8, 5, 1.0, -1),
+    # L >= 8: the time-marching kernel (one segment; T not a multiple of its 8-slice segment)
+    (4, 8, 0.4, 13, 2 / 3, -1),
+    (10, 8, 0.6, 17, -1 / 3, 1),
 ]
 
 
@@ -70,7 +73,7 @@ def test_fp64_apply_matches_oracle(case, gamma5):
     g.close()
 
 
-@pytest.mark.parametrize("case", CASES[:4])
+@pytest.mark.parametrize("case", CASES[:4] + CASES[5:])
 @pytest.mark.parametrize("prec,mode", [(cstar.FP32, 1), (cstar.FP32_BF16LINKS, 2)])
 def test_fp32_forms_match_emulating_oracle(case, prec, mode):
     _setup()
@@ -92,10 +95,10 @@ def test_fp32_forms_match_emulating_oracle(case, prec, mode):
     g.close()
 
 
+@pytest.mark.parametrize("T,L", [(6, 4), (6, 8)])
 @pytest.mark.parametrize("prec", [cstar.FP64, cstar.FP32_BF16LINKS])
-def test_multi_rhs_matches_single(prec):
+def test_multi_rhs_matches_single(prec, T, L):
     _setup()
-    T, L = 6, 4
     su3, th = synth.make_field(T, L, 0.4, 21)
     g = cstar.Gauge(su3, th, 2 / 3)
     masses = [-0.5, -0.1, 0.0, 0.3, 1.2]

@@ -41,14 +41,22 @@ def test_lowest_eigs_tiny_all_kappas(inner):
     g.close()
 
 
-def test_lowest_eigs_returns_eigenvectors():
-    w, su3, th, q = _tiny()
+@pytest.mark.parametrize("lattice", ["tiny", "4x8^3"])
+@pytest.mark.parametrize("inner", [cstar.FP64, cstar.FP32_BF16LINKS])
+def test_lowest_eigs_returns_eigenvectors(lattice, inner):
+    """Eigenpairs checked by the oracle's operator: ||Q v - lambda v|| within the reported bound.
+    The 4x8^3 lattice runs the time-marching apply and its fused Chebyshev epilogue."""
+    if lattice == "tiny":
+        w, su3, th, q = _tiny()
+    else:
+        su3, th = synth.make_field(4, 8, 0.4, 23, smear_steps=2)
+        q = 2 / 3
     g = cstar.Gauge(su3, th, q)
     op = odirac.Operator(su3, th, q)
     m0 = float(synth.kappa_to_m0(0.11))
     k = 3
     vec = g.new_native(k, cstar.FP64)
-    ev, res, st = g.lowest_eigs(m0, k, cstar.eig_opts(inner=cstar.FP64, tol=1e-12), evecs=vec)
+    ev, res, st = g.lowest_eigs(m0, k, cstar.eig_opts(inner=inner, tol=1e-12), evecs=vec)
     canon = torch.empty((k,) + op.shape, dtype=torch.complex128, device="cuda")
     g.unpack(vec, canon, cstar.FP64, k)
     torch.cuda.synchronize()
@@ -85,4 +93,36 @@ def test_pfaffian_sign_rough_fields_with_negative_signs(seed, eps):
     refp = np.array([osign.sign_pfaffian(op, m) for m in path])
     assert np.array_equal(ref, refp)
     assert np.array_equal(signs, ref), (signs, ref)
+    g.close()
+
+
+def test_single_16_4_eigenvalues_fp32_vs_fp64():
+    """16^4 workload (eps 0.2, q = -1/3, kappa 0.1365), k = 8: the plain FP64 form's
+    eigenpairs are certified by the oracle's operator (||Q v - lambda v|| within the
+    reported bound), and the mixed form (BF16/FP32 links in the filter, FP64
+    Rayleigh-Ritz) agrees with them within the residual bounds at tol 1e-10."""
+    w = synth.WORKLOADS["single_16^4"]
+    T, L, q = w["T"], w["L"], w["q"][0]
+    su3, th = synth.make_field(T, L, w["eps"], w["seed"])
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    m0 = float(synth.kappa_to_m0(w["kappas"][0]))
+    k = 8
+    vec = g.new_native(k, cstar.FP64)
+    e64, r64, s64 = g.lowest_eigs(m0, k, cstar.eig_opts(inner=cstar.FP64, tol=1e-10, max_iter=1000), evecs=vec)
+    canon = torch.empty((k,) + op.shape, dtype=torch.complex128, device="cuda")
+    g.unpack(vec, canon, cstar.FP64, k)
+    torch.cuda.synchronize()
+    V = canon.cpu().numpy()
+    for i in range(k):
+        v = V[i] / np.linalg.norm(V[i])
+        r = np.linalg.norm(op.Q(v, m0) - e64[i] * v)
+        assert r <= r64[i] * 1.01 + 1e-12
+    for inner in (cstar.FP32_BF16LINKS, cstar.FP32):
+        em, rm, sm = g.lowest_eigs(m0, k, cstar.eig_opts(inner=inner, tol=1e-10, max_iter=1000))
+        err = np.abs(em - e64)
+        print(f"16^4 k=8 inner={inner}: |lambda - lambda_fp64| = {err}, FP64 form {s64.iterations} it / "
+              f"{s64.applies_fp64} applies, mixed {sm.iterations} it / {sm.applies_inner} + {sm.applies_fp64} applies")
+        assert np.all(err <= rm + r64 + 1e-13)
+        assert np.all(err <= 1e-10 * np.maximum(np.abs(e64), 1e-3) + rm + r64)
     g.close()
