@@ -471,6 +471,53 @@ __device__ __forceinline__ void finish_site(const Geo &g, V *__restrict__ out, c
     SpinorIO<R>::store(out, g, p, h, c, acc);
 }
 
+// Exchange of one value with another lane of the wave (LDS crossbar, no memory access).
+__device__ __forceinline__ float lane_get(int src, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(int src, double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Both x3 hops of a site through the wave (L <= 32, so the 2L lanes of an x3
+// row -- lane = 2 x3 + copy -- lie in one wave): every lane sends the
+// projected (1 - g3) psi(x) to its backward neighbour and V(x,3)^H (1 + g3) psi(x),
+// formed with its own link, to its forward neighbour; a hop across the x3
+// boundary lands on the other copy.  No spinor or backward link is loaded.
+template <class Fmt, int LOG2L>
+__device__ __forceinline__ void hop_x3_wave(const Geo &g, const GaugeDev &d, int p, int h, int c, int x3,
+                                            const cx<typename Prec<Fmt>::R> v[12],
+                                            cx<typename Prec<Fmt>::R> acc[12]) {
+    using R = typename Prec<Fmt>::R;
+    constexpr int L = 1 << LOG2L;
+    static_assert(L <= 32, "an x3 row must fit in one wave");
+    const int lane = threadIdx.x & 63;
+    const int rowbase = lane & ~(2 * L - 1);
+    const int src_f = x3 < L - 1 ? lane + 2 : rowbase + (1 - c);                // site x + 3
+    const int src_b = x3 > 0 ? lane - 2 : rowbase + 2 * (L - 1) + (1 - c);      // site x - 3
+    Link<R> Lk;
+    Fmt::load(d, g, p, 3, h, c ? R(-1) : R(1), Lk);  // V(x,3) of this lane's copy
+    {
+        cx<R> hh[6], gg[6];
+        project<3, 1>(v, hh);
+        link_mul<Fmt, true>(Lk, hh, gg);
+#pragma unroll
+        for (int i = 0; i < 6; i++) hh[i] = {lane_get(src_b, gg[i].re), lane_get(src_b, gg[i].im)};
+        accumulate<3, 1>(acc, hh);
+    }
+    {
+        cx<R> hh[6], gg[6];
+        project<3, -1>(v, gg);
+#pragma unroll
+        for (int i = 0; i < 6; i++) hh[i] = {lane_get(src_f, gg[i].re), lane_get(src_f, gg[i].im)};
+        link_mul<Fmt, false>(Lk, hh, gg);
+        accumulate<3, -1>(acc, gg);
+    }
+}
+
 template <class Fmt, int LOG2L, int RX1, int RX2, int TB>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
@@ -565,11 +612,15 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
             // opaque coordinates: recomputed per slice rather than held across the loop
             int cj_ = c, x1j = x1, x2j = x2, x3j = x3;
             asm volatile("" : "+v"(cj_), "+v"(x1j), "+v"(x2j), "+v"(x3j));
+            if constexpr (LOG2L <= 5) {
+                hop_x3_wave<Fmt, LOG2L>(g, d, ps, hs, cj_, x3j, v, acc);
+            } else {
+                hop_pair<Fmt, 3, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            }
+            pin(acc);
             hop_pair<Fmt, 1, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
             pin(acc);
             hop_pair<Fmt, 2, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
-            pin(acc);
-            hop_pair<Fmt, 3, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
             pin(acc);
         }
     }
