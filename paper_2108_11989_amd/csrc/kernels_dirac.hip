@@ -518,6 +518,36 @@ __device__ __forceinline__ void hop_x3_wave(const Geo &g, const GaugeDev &d, int
     }
 }
 
+// One half of hop_pair from memory, with the link already loaded (forward) or
+// loaded here (backward).
+template <class Fmt, int MU, int LOG2L>
+__device__ __forceinline__ void hop_fwd_mem(const Geo &g, const typename Prec<Fmt>::V *__restrict__ in, int p, int c,
+                                            int t, int x1, int x2, int x3, const Link<typename Prec<Fmt>::R> &L,
+                                            cx<typename Prec<Fmt>::R> acc[12]) {
+    using R = typename Prec<Fmt>::R;
+    const Hop n = hop_fwd<MU, LOG2L>(g, t, x1, x2, x3);
+    cx<R> v[12], hh[6], gg[6];
+    SpinorIO<R>::load(in, g, 1 - p, n.h, c ^ n.flip, v);
+    project<MU, -1>(v, hh);
+    link_mul<Fmt, false>(L, hh, gg);
+    accumulate<MU, -1>(acc, gg);
+}
+template <class Fmt, int MU, int LOG2L>
+__device__ __forceinline__ void hop_bwd_mem(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
+                                            int p, int c, int t, int x1, int x2, int x3,
+                                            cx<typename Prec<Fmt>::R> acc[12]) {
+    using R = typename Prec<Fmt>::R;
+    const Hop n = hop_bwd<MU, LOG2L>(g, t, x1, x2, x3);
+    const int cn = c ^ n.flip;
+    Link<R> L;
+    Fmt::load(d, g, 1 - p, MU, n.h, cn ? R(-1) : R(1), L);
+    cx<R> v[12], hh[6], gg[6];
+    SpinorIO<R>::load(in, g, 1 - p, n.h, cn, v);
+    project<MU, 1>(v, hh);
+    link_mul<Fmt, true>(L, hh, gg);
+    accumulate<MU, 1>(acc, gg);
+}
+
 template <class Fmt, int LOG2L, int RX1, int RX2, int TB>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
@@ -541,12 +571,15 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     const int c = lane & 1;
     const int x3 = (lane >> 1) & (L - 1);
     const int row = lane >> (LOG2L + 1);
-    const int x2 = tile2 * RX2 + row % RX2;
+    const int x2_in = row % RX2;
+    const int x2 = tile2 * RX2 + x2_in;
     const int x1 = tile1 * RX1 + row / RX2;
     const int t0 = seg * TB;
     const int t1 = min(t0 + TB, g.T);
     const double mass = masses ? masses[j] : mass0;
     const R dm = R(4.0 + mass);
+    // x2 exchange: [forward / backward payload][half-spinor component][lane]
+    __shared__ cx<R> xch[2][6][RX1 * RX2 * (2 << LOG2L)];
     const typename Prec<Fmt>::V *inj = in + j * stride;
     typename Prec<Fmt>::V *outj = out + j * stride;
     const long joff = j * stride;
@@ -618,9 +651,43 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
                 hop_pair<Fmt, 3, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
             }
             pin(acc);
-            hop_pair<Fmt, 1, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            // x2 hops: each lane publishes (1 - g2) psi(x) and V(x,2)^H (1 + g2) psi(x)
+            // in LDS; neighbours inside the workgroup's tile read them, rows on
+            // the tile's x2 faces fetch from memory
+            Link<R> L2;
+            Fmt::load(d, g, ps, 2, hs, csg, L2);
+            {
+                cx<R> hh[6], gg[6];
+                project<2, -1>(v, hh);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[0][i][lane] = hh[i];
+                project<2, 1>(v, hh);
+                link_mul<Fmt, true>(L2, hh, gg);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[1][i][lane] = gg[i];
+            }
+            __syncthreads();
+            if (x2_in + 1 < RX2) {
+                cx<R> hh[6], gg[6];
+#pragma unroll
+                for (int i = 0; i < 6; i++) hh[i] = xch[0][i][lane + 2 * L];
+                link_mul<Fmt, false>(L2, hh, gg);
+                accumulate<2, -1>(acc, gg);
+            } else {
+                hop_fwd_mem<Fmt, 2, LOG2L>(g, inj, ps, cj_, ts, x1j, x2j, x3j, L2, acc);
+            }
             pin(acc);
-            hop_pair<Fmt, 2, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            if (x2_in > 0) {
+                cx<R> gg[6];
+#pragma unroll
+                for (int i = 0; i < 6; i++) gg[i] = xch[1][i][lane - 2 * L];
+                accumulate<2, 1>(acc, gg);
+            } else {
+                hop_bwd_mem<Fmt, 2, LOG2L>(g, d, inj, ps, cj_, ts, x1j, x2j, x3j, acc);
+            }
+            pin(acc);
+            __syncthreads();  // the exchange buffer is rewritten in the next slice
+            hop_pair<Fmt, 1, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
             pin(acc);
         }
     }
