@@ -559,10 +559,12 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     constexpr int N1 = L / RX1, N2 = L / RX2;
     const int nseg = (g.T + TB - 1) / TB;
     const int per_rhs = N1 * N2 * nseg;
+    // right-hand side fastest: the workgroups of one tile for all right-hand
+    // sides run together on one XCD and share its link and clover lines in L2
     const int item = xcd_tile(gridDim.x);
-    const int j = item / per_rhs;
-    if (j >= nrhs) return;
-    int r = item - j * per_rhs;
+    const int j = item % nrhs;
+    int r = item / nrhs;
+    if (r >= per_rhs) return;
     const int tile2 = r % N2;
     r /= N2;
     const int tile1 = r % N1;
