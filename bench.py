@@ -242,6 +242,8 @@ def main():
                     help="learned vs plain: cold eigensolves at the first n path masses after the timed region (0: skip)")
     ap.add_argument("--compare-path", action="store_true",
                     help="learned vs plain over the whole path (three Pfaffian signs; minutes), instead of the timed step")
+    ap.add_argument("--learned", action="store_true",
+                    help="timed step with the learned preconditioner (trained before the timed region)")
     ap.add_argument("--train-fields", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
@@ -286,12 +288,18 @@ def main():
         return
 
     charges = [float(x) for x in w["q"]]
+    net_timed = None
+    if args.learned:
+        net_timed, _ = train_network(args, w, q, float(masses[0]))
+        opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, use_nn=1)
 
     def step():
         """One Pfaffian sign over the whole path for every quark charge of the workload."""
         out = []
         for qc in charges:
             g = cstar.Gauge(su3_d, th_d, qc, synth.CSW_SU3, synth.CSW_U1)
+            if net_timed is not None:
+                net_timed.attach(g)
             g.timing(True)
             signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
             out.append((signs, rep, g.read_timing()))
@@ -356,7 +364,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": f"{T}x{L}^3", "sites_doubled": nsites2,
                    "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol,
-                   "inner": args.inner, "charges": charges, "s_per_sign": dt / args.steps / len(charges),
+                   "inner": args.inner, "learned": bool(args.learned), "charges": charges, "s_per_sign": dt / args.steps / len(charges),
                    "mass_points_solved": [r.n_points for _, r, _ in res],
                    "crossings": [r.n_crossings for _, r, _ in res],
                    "signs": ["".join("+" if v > 0 else "-" for v in sg) for sg, _, _ in res]},
