@@ -242,6 +242,7 @@ def main():
                     help="learned vs plain: cold eigensolves at the first n path masses after the timed region (0: skip)")
     ap.add_argument("--compare-path", action="store_true",
                     help="learned vs plain over the whole path (three Pfaffian signs; minutes), instead of the timed step")
+    ap.add_argument("--charges", default="", help="comma-separated indices of the workload's quark charges (default: all)")
     ap.add_argument("--learned", action="store_true",
                     help="timed step with the learned preconditioner (trained before the timed region)")
     ap.add_argument("--train-fields", type=int, default=8)
@@ -288,6 +289,8 @@ def main():
         return
 
     charges = [float(x) for x in w["q"]]
+    if args.charges:
+        charges = [charges[int(i)] for i in args.charges.split(",")]
     net_timed = None
     if args.learned:
         net_timed, _ = train_network(args, w, q, float(masses[0]))
@@ -301,10 +304,11 @@ def main():
             if net_timed is not None:
                 net_timed.attach(g)
             g.timing(True)
+            tq = time.perf_counter()
             signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
             out.append((signs, rep, g.read_timing()))
             g.close()
-            log(f"[bench]   q = {qc:+.4f}: {rep.n_points} mass points, {rep.applies} applies, "
+            log(f"[bench]   q = {qc:+.4f}: {time.perf_counter() - tq:.1f} s, {rep.n_points} mass points, {rep.applies} applies, "
                 f"crossings {rep.n_crossings}, signs {''.join('+' if v > 0 else '-' for v in signs)}")
         return out
 
