@@ -374,7 +374,8 @@ def main():
                    "signs": ["".join("+" if v > 0 else "-" for v in sg) for sg, _, _ in res]},
         "roofline": {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic({0: "fp64", 1: "fp32", 2: "bf16"}[dom], rhs / max(launches, 1)),
+                     "traffic": (measured_traffic({0: "fp64", 1: "fp32", 2: "bf16"}[dom], rhs / max(launches, 1))
+                                 if args.workload == "batched_32^4" else None),
                      "algorithmic_bytes_per_launch": byts / max(launches, 1),
                      "avg_launch_ms": ms[dom] / max(launches, 1), "rhs_per_launch": rhs / max(launches, 1)},
         "cpu_baseline": cpu,
