@@ -120,13 +120,33 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
     };
     // path points at or above m_max need no solve: no eigenvalue reaches zero
     // there and the count of negative eigenvalues is the even large-mass one
+    std::vector<double> need;  // path points below m_max, ascending
     for (double m : uniq)
-        if (m < m_max && !solve(m)) return fail(CSTAR_ENOCONV, "pfaffian_sign: eigenvalue provider failed");
-    const double top = uniq.back();
+        if (m < m_max) need.push_back(m);
     if (!solve(m_max)) return fail(CSTAR_ENOCONV, "pfaffian_sign: eigenvalue provider failed");
+    // step A downwards from m_max to the lowest path point: m <- m - c lambda_bar(m)
+    if (!need.empty()) {
+        const double target = need.front();
+        double cur = m_max;
+        while (cur > target) {
+            const Point &p = pts[cur];
+            const double step = p.amb ? 0.0 : c * std::max(p.lb - p.lb_err, 0.0);
+            double mnew = cur - step;
+            // near a crossing the steps shrink geometrically: leave the rest of
+            // the way to the segment certification (midpoint splits)
+            if (!(step >= 0.25 * (cur - target)) || mnew <= target) mnew = target;
+            if ((int)pts.size() >= max_points) return fail(CSTAR_ENOCONV, "pfaffian_sign: too many mass points");
+            if (!solve(mnew)) return fail(CSTAR_ENOCONV, "pfaffian_sign: eigenvalue provider failed");
+            cur = mnew;
+        }
+    }
 
-    // certify segments, inserting step-A points where needed
+    // certify segments, inserting step-A points where needed.  A segment
+    // certified by exclusion (rule (i)) holds no crossing at all, so a path
+    // point inside it needs no solve; a path point inside a segment certified
+    // by counting (rule (ii)) is solved, which splits the segment.
     std::map<double, int> seg_cross;  // key: lower end
+    std::map<double, bool> seg_excl;  // certified by exclusion
     bool ambiguous = false;
     for (;;) {
         bool inserted = false;
@@ -136,11 +156,13 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             const double D = b.m - a.m;
             if (!a.amb && !b.amb && (a.lb - a.lb_err) + (b.lb - b.lb_err) > D) {
                 seg_cross[a.m] = 0;
+                seg_excl[a.m] = true;
                 continue;
             }
             int par = 0;
             if (count_rule(a, b, &par)) {
                 seg_cross[a.m] = par;
+                seg_excl[a.m] = false;
                 continue;
             }
             // split: the step-A point a + c*lambda_bar(a) when it makes real
@@ -154,6 +176,7 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             if (D < 1e-12 * std::max(1.0, std::fabs(a.m))) {
                 ambiguous = true;
                 seg_cross[a.m] = 0;
+                seg_excl[a.m] = false;
                 continue;
             }
             if ((int)pts.size() >= max_points) return fail(CSTAR_ENOCONV, "pfaffian_sign: too many mass points");
@@ -176,15 +199,33 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             if (!placed) {
                 ambiguous = true;
                 seg_cross[a_m] = 0;
+                seg_excl[a_m] = false;
                 continue;
             }
             inserted = true;
             break;  // the map changed: rescan
         }
+        if (inserted) continue;
+        // every segment is certified: solve the path points that lie inside a
+        // segment certified only by counting
+        for (double m : need) {
+            if (pts.count(m)) continue;
+            auto hi = pts.upper_bound(m);
+            if (hi == pts.begin() || hi == pts.end()) continue;
+            const double a_m = std::prev(hi)->first;
+            if (seg_excl.count(a_m) && seg_excl[a_m]) continue;
+            if ((int)pts.size() >= max_points) return fail(CSTAR_ENOCONV, "pfaffian_sign: too many mass points");
+            if (!solve(m)) return fail(CSTAR_ENOCONV, "pfaffian_sign: eigenvalue provider failed");
+            seg_cross.erase(a_m);
+            seg_excl.erase(a_m);
+            inserted = true;
+        }
         if (!inserted) break;
     }
 
-    // parity of crossings above each path point; the top point has an even count
+    // parity of crossings above each solved point (the top point has an even
+    // count); a path point that was not solved lies in a crossing-free segment
+    // and has the parity of that segment's upper end
     std::map<double, int> parity_above;
     int acc = 0;
     for (auto it = pts.rbegin(); it != pts.rend(); ++it) {
@@ -194,14 +235,19 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
     int total = 0;
     for (auto &kv : seg_cross)
         if (kv.first >= uniq.front()) total += kv.second;
-    (void)top;
     cstar_status st = CSTAR_OK;
     for (int i = 0; i < n; i++) {
         if (path[i] >= m_max) {
             sign_out[i] = 1;
             continue;
         }
-        const Point &p = pts[path[i]];
+        auto itp = pts.find(path[i]);
+        if (itp == pts.end()) {
+            const double upper = pts.upper_bound(path[i])->first;
+            sign_out[i] = parity_above[upper] ? -1 : 1;
+            continue;
+        }
+        const Point &p = itp->second;
         if (p.amb || ambiguous) {
             sign_out[i] = p.amb ? 0 : (parity_above[path[i]] ? -1 : 1);
             if (p.amb) st = CSTAR_EAMBIG;

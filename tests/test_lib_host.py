@@ -68,21 +68,36 @@ def test_sign_driver_on_closed_form_flows(seed):
     for m, sg in zip(path, signs):
         n = np.sum(a + s * m < 0)
         assert sg == (-1 if (n - n_top) % 2 else 1), (m, n, n_top)
-    assert rep.n_points >= len(path)
 
 
 def test_sign_driver_step_a_without_crossings():
-    # one flow rising from the target: step A reaches m_max without a decrease
+    # flows rising from the target: the driver solves m_max, steps down by
+    # c * lambda_bar (here past the target, so the target is solved next), and
+    # certifies [target, m_max] with a few exclusion-covered points
     a = np.array([0.05, 0.3, 0.9, 1.4])
     s = np.array([0.9, 0.7, 0.5, 0.5])
     st, signs, rep = cstar.sign_driver(_provider(a, s), [0.0], k=4, c=1.9, m_max=4.0)
     assert st == cstar.OK and signs[0] == 1
     ms = np.array(rep.m[: rep.n_points])
     lb = np.array(rep.lambda_bar[: rep.n_points])
-    # the solved masses after the target follow m_{n+1} = m_n + c * lambda_bar_n
-    # until they overshoot the top point
-    assert np.isclose(ms[0], 0.0)
+    assert np.isclose(ms[0], 4.0) and np.isclose(ms[1], 0.0)
+    assert np.isclose(lb[0], np.min(a + 4.0 * s))
+    # every neighbouring pair of solved masses is covered by their exclusion intervals
+    order = np.argsort(ms)
+    m_s, l_s = ms[order], lb[order]
+    assert np.all(l_s[:-1] + l_s[1:] > np.diff(m_s))
     assert rep.n_points < 12
+
+
+def test_sign_driver_skips_path_points_inside_exclusion_intervals():
+    # a gapped flow: every path point lies in an exclusion interval, so far fewer
+    # solves than path points are needed and every sign is +1
+    a = np.array([0.8, 1.0, 1.3, 1.6])
+    s = np.array([0.1, -0.1, 0.2, 0.05])
+    path = np.linspace(-1.0, 1.0, 41)
+    st, signs, rep = cstar.sign_driver(_provider(a, s), path, k=4, c=1.9, m_max=2.0)
+    assert st == cstar.OK and np.all(signs == 1)
+    assert rep.n_points < 10
 
 
 def test_sign_driver_ambiguous_path_point():
