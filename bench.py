@@ -187,7 +187,7 @@ def kernel_probe(args, su3_d, th_d, q, T, L):
     from paper_2108_11989_amd import cstar, synth
     g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
     nsites2 = 2 * T * L ** 3
-    nb = args.probe_nrhs or (2 * args.k + max(12, args.k))
+    nb = args.probe_nrhs or (2 * args.k + max(8, args.k))
     res = {}
     for prec, name in [(cstar.FP64, "fp64"), (cstar.FP32, "fp32"), (cstar.FP32_BF16LINKS, "bf16")]:
         for nrhs in (1, nb):
@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--workload", default="batched_32^4")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--block", type=int, default=0, help="eigensolver block size (0: 2k + max(8, k))")
     ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--path-points", type=int, default=0, help="use only the first n kappas (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -277,7 +278,7 @@ def main():
     kappas = w["kappas"] if args.path_points <= 0 else w["kappas"][: args.path_points]
     masses = np.asarray(synth.kappa_to_m0(kappas), dtype=np.float64)
     inner = {"bf16": cstar.FP32_BF16LINKS, "fp32": cstar.FP32, "fp64": cstar.FP64}[args.inner]
-    opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000)
+    opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, block=args.block)
     nsites2 = 2 * T * L ** 3
 
     if args.compare_path:
@@ -294,7 +295,7 @@ def main():
     net_timed = None
     if args.learned:
         net_timed, _ = train_network(args, w, q, float(masses[0]))
-        opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, use_nn=1)
+        opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, use_nn=1, block=args.block)
 
     def step():
         """One Pfaffian sign over the whole path for every quark charge of the workload."""

@@ -118,7 +118,7 @@ typedef struct {
     cstar_prec inner;        /* precision of the filter applies (FP64 or an FP32 form) */
     double tol;              /* target: residual ||Q v - lambda v|| <= tol * max(|lambda|, lambda_floor) */
     int max_iter;            /* outer iterations */
-    int block;               /* vectors per block (>= 2k; 0 = automatic) */
+    int block;               /* vectors per block (>= 2k, <= 64; 0 = 2k + max(8, k)) */
     int degree;              /* Chebyshev filter degree (0 = automatic) */
     int use_nn;              /* 1: learned preconditioner attached to the handle, if any */
     int warm_start;          /* 1: start from the Ritz block of this handle's previous converged call */

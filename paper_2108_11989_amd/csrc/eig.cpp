@@ -374,7 +374,7 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     if (!(o.tol > 0) || o.max_iter < 1) return fail(CSTAR_EINVAL, "q_lowest_eigs: bad tol/max_iter");
     // guard vectors: the low spectrum of smooth fields comes in near-degenerate
     // multiplets; the block must hold a whole multiplet beyond the wanted ones
-    int nb = o.block > 0 ? o.block : 2 * k + std::max(12, k);
+    int nb = o.block > 0 ? o.block : 2 * k + std::max(8, k);
     nb = std::max(nb, 2 * k);
     if (nb > 64) return fail(CSTAR_EINVAL, "q_lowest_eigs: block must be <= 64");
     int deg = o.degree > 0 ? o.degree : 24;
