@@ -618,8 +618,9 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
                 fp64_filter = true;
             stall = 0;
         }
-        // filter degree: about two e-folds of damping per iteration between the
-        // slowest wanted Ritz value and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up),
+        // filter degree: about three e-folds of damping per iteration between the
+        // slowest wanted Ritz value and the cut, ln T_d(x) ~ 2 d sqrt((a_cut - theta)/b_up)
+        // (measured at 32^4: 1.5 / sqrt(gap / b_up) beats 0.7, 1, 2 and 3 times that),
         // but bounded so that the filter's gain across the wanted values stays
         // below 1e4 (inner precision) / 1e8 (FP64): a larger spread lets the
         // lowest mode swamp every column of the filtered block.
@@ -630,7 +631,7 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
                 const double gk = std::max(acut - theta[2 * k - 1], 1e-300);
                 const double g0 = std::max(acut - theta[0], gk);
                 const double sk = std::sqrt(gk / bup), s0 = std::sqrt(g0 / bup);
-                const double d_want = 1.0 / sk;
+                const double d_want = 1.5 / sk;
                 const double d_range = std::log(fp64_filter ? 1e8 : 1e4) / (2.0 * (s0 - sk) + 1e-300);
                 deg = (int)std::min<double>(deg_max, std::max<double>(8.0, std::min(d_want, d_range)));
             }
