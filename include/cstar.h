@@ -158,7 +158,7 @@ typedef struct {
 } cstar_sign_opts;
 
 typedef struct {
-    int n_points;        /* mass points solved (path points + step-A / bisection points) */
+    int n_points;        /* mass points solved (m_max, step-A, bisection and the path points that need it) */
     double m[512];       /* the masses, in the order solved */
     double lambda_bar[512];
     int n_crossings;     /* certified zero crossings between the target and m_max */
@@ -172,11 +172,14 @@ typedef struct {
  * Sign of the Pfaffian W_sgn(m_i) = sign pf[C T D(m_i)] at every mass of
  * m_path (paper: pf[CTD] = prod_n lambda_n, so the sign flips each time an
  * eigenvalue of Q crosses zero as m0 moves, and it is +1 at very large mass).
- * The flow is followed upwards from min(m_path) to m_max with step A of the
- * paper (m <- m + c*lambda_bar while lambda_bar grows, using the
- * Feynman-Hellmann bound |lambda_n'(m0)| <= 1); a segment where the bound
- * does not exclude a crossing is resolved by counting eigenvalues that pass
- * zero between certified levels, splitting the segment if needed.
+ * The flow is followed down from m_max (above which no eigenvalue can reach
+ * zero) to min(m_path) with step A of the paper (m <- m - c*lambda_bar(m);
+ * the Feynman-Hellmann bound |lambda_n'(m0)| <= 1 excludes a crossing within
+ * lambda_bar of a solved mass); a segment where these exclusion intervals
+ * do not cover it is resolved by counting eigenvalues that pass zero between
+ * certified levels, splitting the segment if needed.  A path point is solved
+ * only when it lies in a segment certified by counting; inside an
+ * exclusion-covered segment it has the sign of the segment's upper end.
  * m_path: host[n], any order.  sign_out: host[n], +1 or -1.  report: nullable.
  * Errors: EINVAL; EAMBIG (an eigenvalue within its error bound of zero at a
  * path point; sign_out holds 0 there); ENOCONV; ENOMEM; EDEVICE.

@@ -6,8 +6,10 @@
 // above which no crossing can occur).  Since Q'(m) = g5, every eigenvalue
 // moves with |lambda_n'(m)| <= 1 (Feynman-Hellmann), hence
 //   (exclusion) no crossing in (m - lambda_bar(m), m + lambda_bar(m)),
-// which is what step A uses: m <- m + c lambda_bar(m), c slightly below 2.
+// which is what step A uses: m <- m -+ c lambda_bar(m), c slightly below 2.
 //
+// Order: m_max is solved first, then step A walks down to the lowest path
+// point; then the segments between solved masses are certified:
 // A segment [a,b] of solved masses is certified
 //   (i)  crossing-free when the exclusion intervals of a and b cover it:
 //        (lambda_bar(a) - err_a) + (lambda_bar(b) - err_b) > b - a;
@@ -18,8 +20,11 @@
 //        has the parity of  #{g < lambda(b) < 0} - #{g < lambda(a) < 0};
 //   (iii) otherwise a new mass is solved inside the segment (the step-A point
 //        a + c lambda_bar(a), or the midpoint) and both halves are certified.
-// Above m_max (a mass beyond which D has no zero mode) the count of negative
-// eigenvalues is that of the large-mass limit, which is even.
+// A path point that is not solved lies in a segment certified by (i), so it
+// has the parity of the segment's upper end; one in a segment certified only
+// by (ii) is solved, which splits that segment.  Above m_max (a mass beyond
+// which D has no zero mode) the count of negative eigenvalues is that of the
+// large-mass limit, which is even.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
