@@ -80,13 +80,16 @@ struct ApplyArgs {
     int gamma5;
     const double *masses_dev;  // device [nrhs] (nullptr: use mass0)
     double mass0;
-    // optional epilogue: out = ea * ([g5] D in) + eb * y + ec * z + ew[j] * w  (y, z, w: same layout and
-    // stride; w needs y; ew: device coefficients per right-hand side, float for the FP32 forms, double for FP64)
+    // optional epilogue: out = ea * ([g5] D in) + eb * y + ec * z + ew[j] * w  (each of y, z, w optional,
+    // same layout and stride; ew: device coefficients per right-hand side, float for the FP32 forms,
+    // double for FP64)
     const void *y = nullptr;
     const void *z = nullptr;
     double ea = 1.0, eb = 0.0, ec = 0.0;
     const void *w = nullptr;
     const void *ew = nullptr;
+    // with gamma5: Q + shift = g5 (D + shift g5), a spin-dependent local mass
+    double shift = 0.0;
 };
 hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s);
 // launch_apply on the handle's stream, with event timing when enabled (timing.cpp)

@@ -142,8 +142,9 @@ hipError_t q64(Ctx &c, const double2 *in, double2 *out, int nv, double ea = 1.0,
 }
 hipError_t q32(Ctx &c, cstar_prec prec, const float4 *in, float4 *out, int nv, double ea = 1.0,
                const float4 *y = nullptr, double eb = 0.0, const float4 *z = nullptr, double ec = 0.0,
-               const float4 *w = nullptr, const float *ew = nullptr) {
+               const float4 *w = nullptr, const float *ew = nullptr, double shift = 0.0) {
     ApplyArgs a{in, out, (long)c.w->n / 2 * (long)sizeof(float4), nv, 1, nullptr, c.m};
+    a.shift = shift;
     a.y = y;
     a.z = z;
     a.ea = ea;
@@ -346,10 +347,14 @@ cstar_status filter_deflated(Ctx &c, cstar_prec prec, const double2 *X, const do
     CSTAR_HIP(hipMemsetAsync(cur, 0, vb, c.s));
     CSTAR_HIP(launch_lincomb32(2 * n * nv, (float)(sig[1] / e), (const float *)Rf, 0.f, (float *)cur, 0.f, nullptr,
                                c.s));
+    // A - cen = (Q - s)(Q + s), s = sqrt(cen): the shifts enter the local mass
+    // term, so the second apply needs no extra read of Z_j
+    const double sh = std::sqrt(cen);
     for (int j = 1; j < deg; j++) {
         const double a = 2.0 * sig[j + 1] / e;
-        CSTAR_HIP(q32(c, prec, cur, tq, nv));
-        CSTAR_HIP(q32(c, prec, tq, nxt, nv, a, cur, -a * cen, prev, -sig[j] * sig[j + 1], Rf, w->coef + (size_t)j * w->nb));
+        CSTAR_HIP(q32(c, prec, cur, tq, nv, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr, nullptr, sh));
+        CSTAR_HIP(q32(c, prec, tq, nxt, nv, a, nullptr, 0.0, prev, -sig[j] * sig[j + 1], Rf,
+                      w->coef + (size_t)j * w->nb, -sh));
         float4 *t = prev;
         prev = cur;
         cur = nxt;

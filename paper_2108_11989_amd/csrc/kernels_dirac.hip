@@ -228,12 +228,13 @@ __device__ __forceinline__ void pin(cx<R> acc[12]) {
 // without another pass over memory).
 template <class V>
 struct Epi {
-    const V *y, *z;
+    const V *y, *z;     // optional operands (null: none)
     float a, b, c;      // FP32 forms
     double ad, bd, cd;  // FP64 form
     int on;
     const V *w;         // optional fourth operand (null: none)
     const void *ew;     // its coefficients: float [nrhs] (FP32 forms) or double [nrhs] (FP64)
+    double shift;       // Q + shift (with g5): local mass 4+m+shift on spins 0,1 and 4+m-shift on 2,3
 };
 
 template <class R, class V>
@@ -245,13 +246,20 @@ __device__ __forceinline__ void apply_epilogue(const Geo &g, const Epi<V> &ep, i
     const R b = sizeof(R) == 8 ? R(ep.bd) : R(ep.b);
     const R cc = sizeof(R) == 8 ? R(ep.cd) : R(ep.c);
     cx<R> w[12];
-    SpinorIO<R>::load(ep.y + joff, g, p, h, c, w);
+    if (ep.y) {
+        SpinorIO<R>::load(ep.y + joff, g, p, h, c, w);
 #pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = {fma(b, w[k].re, a * acc[k].re), fma(b, w[k].im, a * acc[k].im)};
-    pin(acc);
-    SpinorIO<R>::load(ep.z + joff, g, p, h, c, w);
+        for (int k = 0; k < 12; k++) acc[k] = {fma(b, w[k].re, a * acc[k].re), fma(b, w[k].im, a * acc[k].im)};
+    } else {
 #pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = {fma(cc, w[k].re, acc[k].re), fma(cc, w[k].im, acc[k].im)};
+        for (int k = 0; k < 12; k++) acc[k] = scale(acc[k], a);
+    }
+    if (ep.z) {
+        pin(acc);
+        SpinorIO<R>::load(ep.z + joff, g, p, h, c, w);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = {fma(cc, w[k].re, acc[k].re), fma(cc, w[k].im, acc[k].im)};
+    }
     if (ep.w) {
         pin(acc);
         const R e = reinterpret_cast<const R *>(ep.ew)[j];
@@ -288,12 +296,12 @@ __device__ __forceinline__ void site_apply(const Geo &g, const GaugeDev &d, cons
 #pragma unroll
     for (int k = 0; k < 12; k++) sw[k] = {R(0), R(0)};
     clover_add<R>(d, g, p, h, c, chi, sw);
-    const R dm = R(4.0 + mass);
+    const R dmu = R(4.0 + mass + ep.shift), dml = R(4.0 + mass - ep.shift);
     const R mh = R(-0.5);
     const R s5 = gamma5 ? R(-1) : R(1);
 #pragma unroll
     for (int k = 0; k < 12; k++) {
-        cx<R> o = sw[k] + scale(chi[k], dm);
+        cx<R> o = sw[k] + scale(chi[k], k < 6 ? dmu : dml);
         o = {o.re + mh * acc[k].re, o.im + mh * acc[k].im};
         if (k >= 6) o = scale(o, s5);
         acc[k] = o;
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     const int t0 = seg * TB;
     const int t1 = min(t0 + TB, g.T);
     const double mass = masses ? masses[j] : mass0;
-    const R dm = R(4.0 + mass);
+    const R dmu = R(4.0 + mass + ep.shift), dml = R(4.0 + mass - ep.shift);
     // x2 exchange: [forward / backward payload][half-spinor component][lane]
     __shared__ cx<R> xch[2][6][RX1 * RX2 * (2 << LOG2L)];
     const typename Prec<Fmt>::V *inj = in + j * stride;
@@ -641,7 +649,7 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
             pin(acc);
             clover_add<R>(d, g, ps, hs, c, v, acc);
 #pragma unroll
-            for (int k = 0; k < 12; k++) acc[k] = scale(acc[k] + scale(v[k], dm), R(-2));
+            for (int k = 0; k < 12; k++) acc[k] = scale(acc[k] + scale(v[k], k < 6 ? dmu : dml), R(-2));
             project<0, 1>(v, hb);
             pin(acc);
             // opaque coordinates: recomputed per slice rather than held across the loop
@@ -710,8 +718,8 @@ constexpr int march_rx1(int rows) { return rows >= 64 ? 8 : rows >= 16 ? 4 : 2; 
 template <class Fmt, int LOG2L>
 static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
     using V = typename Prec<Fmt>::V;
-    Epi<V> ep{(const V *)a.y, (const V *)(a.z ? a.z : a.y), (float)a.ea, (float)a.eb, (float)(a.z ? a.ec : 0.0),
-              a.ea, a.eb, a.z ? a.ec : 0.0, a.y ? 1 : 0, (const V *)(a.y ? a.w : nullptr), a.ew};
+    Epi<V> ep{(const V *)a.y, (const V *)a.z, (float)a.ea, (float)a.eb, (float)a.ec, a.ea, a.eb, a.ec,
+              (a.y || a.z || a.w || a.ea != 1.0) ? 1 : 0, (const V *)a.w, a.ew, a.shift};
     const long st = a.stride / (long)sizeof(V);
     const int ntiles = (4 * g.Vh + 255) / 256;
     if constexpr (LOG2L >= 3) {

@@ -60,7 +60,7 @@ hipError_t handle_apply(cstar_gauge *g, cstar_prec prec, const ApplyArgs &a) {
     t->pending.push_back({ea, eb, (int)prec});
     t->launches[prec] += 1;
     t->rhs[prec] += a.nrhs;
-    if (a.y) t->operands[prec] += (long)a.nrhs * ((a.z && a.ec != 0.0) ? 2 : 1) + (a.w ? a.nrhs : 0);
+    t->operands[prec] += (long)a.nrhs * ((a.y ? 1 : 0) + (a.z ? 1 : 0) + (a.w ? 1 : 0));
     if (t->pending.size() >= 4096) return drain(t);
     return hipSuccess;
 }
