@@ -556,7 +556,7 @@ __device__ __forceinline__ void hop_bwd_mem(const Geo &g, const GaugeDev &d, con
     accumulate<MU, 1>(acc, gg);
 }
 
-template <class Fmt, int LOG2L, int RX1, int RX2, int TB>
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, bool EPI>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
     long stride, int nrhs, int gamma5, const double *__restrict__ masses, double mass0,
@@ -632,7 +632,15 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
             }
             link_mul<Fmt, false>(Lt, hf, gf);
             accumulate<0, -1>(acc, gf);
-            finish_site<R, V>(g, outj, ep, j, joff, pm, hm, c, gamma5, acc);
+            if constexpr (EPI) {
+                finish_site<R, V>(g, outj, ep, j, joff, pm, hm, c, gamma5, acc);
+            } else {
+                // no epilogue: the result is -1/2 acc, times g5
+                const R s5 = gamma5 ? R(-1) : R(1);
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[k] = scale(acc[k], k < 6 ? R(-0.5) : R(-0.5) * s5);
+                SpinorIO<R>::store(outj, g, pm, hm, c, acc);
+            }
         }
         if (s < t1) {
             // site s: backward time hop (scaled by -1/2 so that the final -2
@@ -730,8 +738,12 @@ static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
         const int nseg = (g.T + TB - 1) / TB;
         const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * a.nrhs;
         const int nwg = (int)((items + 7) / 8 * 8);
-        hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB>), dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d,
-                           (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
+        if (ep.on)
+            hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true>), dim3(nwg), dim3(March<Fmt>::lanes), 0,
+                               s, g, d, (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
+        else
+            hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false>), dim3(nwg), dim3(March<Fmt>::lanes), 0,
+                               s, g, d, (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
         return;
     }
     if constexpr (LOG2L >= 2) {
