@@ -70,39 +70,49 @@ __device__ __forceinline__ void accumulate(cx<R> acc[12], const cx<R> g[6]) {
 // Block b (b=0: spins 0,1; b=1: spins 2,3) of the Hermitian 6x6 term, index
 // i = 3*spin_in_block + colour: 6 real diagonal entries, then the 15 strictly
 // lower entries M[i][j] (i > j) in row order, off(i,j) = i(i-1)/2 + j.
+// NT: streaming loads, for launches that read each site's clover once (one
+// right-hand side); with several right-hand sides their workgroups read the
+// same lines one after another and the loads keep them in L2.
+template <bool NT, class T>
+__device__ __forceinline__ T clover_ld(const T *p) {
+    if constexpr (NT) return load_nt(p);
+    else return *p;
+}
 template <class R>
 struct CloverIO;
 
 template <>
 struct CloverIO<double> {
+    template <bool NT>
     static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int h, int b, double dg[6],
                                                 cx<double> o[15]) {
         const double2 *q = d.clov64 + (long)(p * 36 + b * 18) * g.Vh + h;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const double2 w = load_nt(&q[(long)k * g.Vh]);
+            const double2 w = clover_ld<NT>(&q[(long)k * g.Vh]);
             dg[2 * k] = w.x;
             dg[2 * k + 1] = w.y;
         }
 #pragma unroll
         for (int k = 0; k < 15; k++) {
-            const double2 w = load_nt(&q[(long)(3 + k) * g.Vh]);
+            const double2 w = clover_ld<NT>(&q[(long)(3 + k) * g.Vh]);
             o[k] = {w.x, w.y};
         }
     }
 };
 template <>
 struct CloverIO<float> {
+    template <bool NT>
     static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int h, int b, float dg[6],
                                                 cx<float> o[15]) {
         const float4 *q = d.clov32 + (long)(p * 18 + b * 9) * g.Vh + h;
-        const float4 w0 = load_nt(&q[0]), w1 = load_nt(&q[g.Vh]);
+        const float4 w0 = clover_ld<NT>(&q[0]), w1 = clover_ld<NT>(&q[g.Vh]);
         dg[0] = w0.x; dg[1] = w0.y; dg[2] = w0.z; dg[3] = w0.w;
         dg[4] = w1.x; dg[5] = w1.y;
         o[0] = {w1.z, w1.w};
 #pragma unroll
         for (int k = 0; k < 7; k++) {
-            const float4 w = load_nt(&q[(long)(2 + k) * g.Vh]);
+            const float4 w = clover_ld<NT>(&q[(long)(2 + k) * g.Vh]);
             o[1 + 2 * k] = {w.x, w.y};
             o[2 + 2 * k] = {w.z, w.w};
         }
@@ -186,14 +196,14 @@ __device__ __forceinline__ void hop_pair(const Geo &g, const GaugeDev &d, const 
 // Clover term of one lane: the physical copy uses the stored blocks M; the
 // conjugate copy uses sigma2 M^* sigma2 (its field strength is conj(F)),
 // evaluated as -sigma2 conj(M sigma2 chi^*) in each chirality block.
-template <class R>
+template <class R, bool NT = true>
 __device__ __forceinline__ void clover_add(const GaugeDev &d, const Geo &g, int p, int h, int c, const cx<R> chi[12],
                                            cx<R> acc[12]) {
 #pragma unroll
     for (int b = 0; b < 2; b++) {
         R dg[6];
         cx<R> o[15];
-        CloverIO<R>::load(d, g, p, h, b, dg, o);
+        CloverIO<R>::template load<NT>(d, g, p, h, b, dg, o);
         cx<R> u[6], w[6];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -556,7 +566,7 @@ __device__ __forceinline__ void hop_bwd_mem(const Geo &g, const GaugeDev &d, con
     accumulate<MU, 1>(acc, gg);
 }
 
-template <class Fmt, int LOG2L, int RX1, int RX2, int TB, bool EPI>
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, bool EPI, bool NTC>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
     long stride, int nrhs, int gamma5, const double *__restrict__ masses, double mass0,
@@ -655,7 +665,7 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[k] = scale(acc[k], R(-0.5));
             pin(acc);
-            clover_add<R>(d, g, ps, hs, c, v, acc);
+            clover_add<R, NTC>(d, g, ps, hs, c, v, acc);
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[k] = scale(acc[k] + scale(v[k], k < 6 ? dmu : dml), R(-2));
             project<0, 1>(v, hb);
@@ -738,12 +748,19 @@ static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
         const int nseg = (g.T + TB - 1) / TB;
         const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * a.nrhs;
         const int nwg = (int)((items + 7) / 8 * 8);
-        if (ep.on)
-            hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true>), dim3(nwg), dim3(March<Fmt>::lanes), 0,
-                               s, g, d, (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
-        else
-            hipLaunchKernelGGL((k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false>), dim3(nwg), dim3(March<Fmt>::lanes), 0,
-                               s, g, d, (const V *)a.in, (V *)a.out, st, a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
+        // epilogue compiled in only where used; clover streamed only when one right-hand side reads it
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d, (const V *)a.in, (V *)a.out, st,
+                               a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
+        };
+        const bool one = a.nrhs == 1;
+        if (ep.on) {
+            if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, true>);
+            else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, false>);
+        } else {
+            if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, true>);
+            else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, false>);
+        }
         return;
     }
     if constexpr (LOG2L >= 2) {
