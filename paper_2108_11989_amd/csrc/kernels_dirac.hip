@@ -257,7 +257,7 @@ __device__ __forceinline__ void apply_epilogue(const Geo &g, const Epi<V> &ep, i
     const R cc = sizeof(R) == 8 ? R(ep.cd) : R(ep.c);
     cx<R> w[12];
     if (ep.y) {
-        SpinorIO<R>::load(ep.y + joff, g, p, h, c, w);
+        SpinorIO<R>::template load<true>(ep.y + joff, g, p, h, c, w);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = {fma(b, w[k].re, a * acc[k].re), fma(b, w[k].im, a * acc[k].im)};
     } else {
@@ -266,14 +266,14 @@ __device__ __forceinline__ void apply_epilogue(const Geo &g, const Epi<V> &ep, i
     }
     if (ep.z) {
         pin(acc);
-        SpinorIO<R>::load(ep.z + joff, g, p, h, c, w);
+        SpinorIO<R>::template load<true>(ep.z + joff, g, p, h, c, w);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = {fma(cc, w[k].re, acc[k].re), fma(cc, w[k].im, acc[k].im)};
     }
     if (ep.w) {
         pin(acc);
         const R e = reinterpret_cast<const R *>(ep.ew)[j];
-        SpinorIO<R>::load(ep.w + joff, g, p, h, c, w);
+        SpinorIO<R>::template load<true>(ep.w + joff, g, p, h, c, w);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = {fma(e, w[k].re, acc[k].re), fma(e, w[k].im, acc[k].im)};
     }

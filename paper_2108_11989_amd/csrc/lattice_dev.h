@@ -132,6 +132,9 @@ __device__ __forceinline__ void store_nt(double2 a, double2 *p) {
 }
 
 // ---------------------------------------------------------------- spinor storage
+// load<true>: streaming loads, for operands that one lane reads once (the
+// epilogue's vectors), so that they do not displace shared link and clover
+// lines from L2.
 // FP64: double2 [p][12][Vh][2];  FP32: float4 [p][6][Vh][2]
 template <class R>
 struct SpinorIO;
@@ -139,13 +142,14 @@ struct SpinorIO;
 template <>
 struct SpinorIO<double> {
     using vec = double2;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const double2 *__restrict__ b, const Geo &g, int p, int h, int c,
                                                 cx<double> v[12]) {
         const double2 *q = b + ((long)p * 12 * g.Vh + h) * 2 + c;
         const long st = 2L * g.Vh;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            const double2 w = q[k * st];
+            const double2 w = NT ? load_nt(&q[k * st]) : q[k * st];
             v[k] = {w.x, w.y};
         }
     }
@@ -161,13 +165,14 @@ struct SpinorIO<double> {
 template <>
 struct SpinorIO<float> {
     using vec = float4;
+    template <bool NT = false>
     static __device__ __forceinline__ void load(const float4 *__restrict__ b, const Geo &g, int p, int h, int c,
                                                 cx<float> v[12]) {
         const float4 *q = b + ((long)p * 6 * g.Vh + h) * 2 + c;
         const long st = 2L * g.Vh;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            const float4 w = q[k * st];
+            const float4 w = NT ? load_nt(&q[k * st]) : q[k * st];
             v[2 * k] = {w.x, w.y};
             v[2 * k + 1] = {w.z, w.w};
         }
