@@ -591,15 +591,15 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     const int c = lane & 1;
     const int x3 = (lane >> 1) & (L - 1);
     const int row = lane >> (LOG2L + 1);
-    const int x2_in = row % RX2;
+    const int x2_in = row % RX2, x1_in = row / RX2;
     const int x2 = tile2 * RX2 + x2_in;
     const int x1 = tile1 * RX1 + row / RX2;
     const int t0 = seg * TB;
     const int t1 = min(t0 + TB, g.T);
     const double mass = masses ? masses[j] : mass0;
     const R dmu = R(4.0 + mass + ep.shift), dml = R(4.0 + mass - ep.shift);
-    // x2 exchange: [forward / backward payload][half-spinor component][lane]
-    __shared__ cx<R> xch[2][6][RX1 * RX2 * (2 << LOG2L)];
+    // exchange buffer: [x2 forward, x2 backward, x1 forward payload][half-spinor component][lane]
+    __shared__ cx<R> xch[3][6][RX1 * RX2 * (2 << LOG2L)];
     const typename Prec<Fmt>::V *inj = in + j * stride;
     typename Prec<Fmt>::V *outj = out + j * stride;
     const long joff = j * stride;
@@ -680,8 +680,9 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
             }
             pin(acc);
             // x2 hops: each lane publishes (1 - g2) psi(x) and V(x,2)^H (1 + g2) psi(x)
-            // in LDS; neighbours inside the workgroup's tile read them, rows on
-            // the tile's x2 faces fetch from memory
+            // in LDS, and (1 - g1) psi(x) for the x1 forward hop; neighbours
+            // inside the workgroup's tile read them, rows on the tile's faces
+            // fetch from memory
             Link<R> L2;
             Fmt::load(d, g, ps, 2, hs, csg, L2);
             {
@@ -693,6 +694,9 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
                 link_mul<Fmt, true>(L2, hh, gg);
 #pragma unroll
                 for (int i = 0; i < 6; i++) xch[1][i][lane] = gg[i];
+                project<1, -1>(v, hh);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[2][i][lane] = hh[i];
             }
             __syncthreads();
             if (x2_in + 1 < RX2) {
@@ -714,8 +718,23 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
                 hop_bwd_mem<Fmt, 2, LOG2L>(g, d, inj, ps, cj_, ts, x1j, x2j, x3j, acc);
             }
             pin(acc);
+            {
+                // x1 forward hop: (1 - g1) V(x,1) psi(x+1); the row x1+1 is RX2 rows on
+                Link<R> L1;
+                Fmt::load(d, g, ps, 1, hs, csg, L1);
+                if (x1_in + 1 < RX1) {
+                    cx<R> hh[6], gg[6];
+#pragma unroll
+                    for (int i = 0; i < 6; i++) hh[i] = xch[2][i][lane + RX2 * 2 * L];
+                    link_mul<Fmt, false>(L1, hh, gg);
+                    accumulate<1, -1>(acc, gg);
+                } else {
+                    hop_fwd_mem<Fmt, 1, LOG2L>(g, inj, ps, cj_, ts, x1j, x2j, x3j, L1, acc);
+                }
+            }
+            pin(acc);
             __syncthreads();  // the exchange buffer is rewritten in the next slice
-            hop_pair<Fmt, 1, LOG2L>(g, d, inj, ps, hs, cj_, ts, x1j, x2j, x3j, acc);
+            hop_bwd_mem<Fmt, 1, LOG2L>(g, d, inj, ps, cj_, ts, x1j, x2j, x3j, acc);
             pin(acc);
         }
     }
