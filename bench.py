@@ -130,6 +130,50 @@ def train_network(args, w, q, m_train):
 FORMS = (("plain_fp64", "fp64", 0), ("plain_mixed", "bf16", 0), ("learned_mixed", "bf16", 1))
 
 
+def compare_lambda_bar(args, su3_d, th_d, q, masses):
+    """lambda_bar by the power method with Chebyshev acceleration on Q^-2 (the
+    paper's step-A solver) against the block eigensolver at the same relative
+    accuracy, cold at each mass: seconds, D applies, the two values.  The block
+    solver runs with the bench's k (a block of 2k + max(8, k) vectors): a
+    smaller block cannot hold the smooth fields' near-degenerate low multiplets
+    of Q^2 and converges very slowly."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    out = []
+    for m in masses:
+        g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, bound, st = g.lambda_bar_power(float(m), tol=args.lbar_tol, max_outer=args.lbar_max_outer,
+                                            raise_on_noconv=False)
+        t_pow = time.perf_counter() - t0
+        conv = bound <= args.lbar_tol * lam
+        g.close()
+        log(f"[bench] lambda_bar at m0={float(m):+.4f}: power {lam:.6f} +- {bound:.1e} in {t_pow:.1f} s "
+            f"({st.applies_fp64} FP64 applies, {st.solves} solves, converged {conv})")
+        g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, res, st2 = g.lowest_eigs(float(m), args.k, cstar.eig_opts(inner=cstar.FP32_BF16LINKS,
+                                                                      tol=args.lbar_tol, max_iter=1000))
+        t_blk = time.perf_counter() - t0
+        g.close()
+        r = {"m0": float(m),
+             "power": {"lambda_bar": lam, "half_width": bound, "converged": bool(conv), "s": t_pow,
+                       "outer": st.outer, "solves": st.solves, "cg_iterations": st.cg_iterations,
+                       "applies_fp64": st.applies_fp64},
+             "block": {"k": args.k, "lambda_bar": float(abs(ev[0])), "resid": float(res[0]), "s": t_blk,
+                          "iterations": st2.iterations, "applies_inner": st2.applies_inner,
+                          "applies_fp64": st2.applies_fp64},
+             "agree": bool(abs(lam - abs(ev[0])) <= bound + float(res[0]))}
+        out.append(r)
+        log(f"[bench] lambda_bar at m0={float(m):+.4f}: block k={args.k} {abs(ev[0]):.6f} +- {res[0]:.1e} in "
+            f"{t_blk:.1f} s ({st2.applies_inner} + {st2.applies_fp64} applies), agree {r['agree']}")
+    return out
+
+
 def compare_forms(args, net, su3_d, th_d, q, masses, full_path):
     """Plain FP64, plain mixed precision and learned + mixed precision: seconds
     and applies per eigensolve at the given masses (cold start), or per
@@ -243,6 +287,11 @@ def main():
                     help="learned vs plain: cold eigensolves at the first n path masses after the timed region (0: skip)")
     ap.add_argument("--compare-path", action="store_true",
                     help="learned vs plain over the whole path (three Pfaffian signs; minutes), instead of the timed step")
+    ap.add_argument("--compare-lbar", type=int, default=0,
+                    help="power method on Q^-2 vs the block eigensolver for lambda_bar at the first n path masses, "
+                         "instead of the timed step")
+    ap.add_argument("--lbar-tol", type=float, default=1e-3, help="relative accuracy of lambda_bar in --compare-lbar")
+    ap.add_argument("--lbar-max-outer", type=int, default=100)
     ap.add_argument("--charges", default="", help="comma-separated indices of the workload's quark charges (default: all)")
     ap.add_argument("--learned", action="store_true",
                     help="timed step with the learned preconditioner (trained before the timed region)")
@@ -287,6 +336,12 @@ def main():
         net.close()
         print(json.dumps({"learned_vs_plain_path": res, "train": info, "workload": args.workload,
                           "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol}), flush=True)
+        return
+
+    if args.compare_lbar > 0:
+        res = compare_lambda_bar(args, su3_d, th_d, q, masses[:args.compare_lbar])
+        print(json.dumps({"lambda_bar_power_vs_block": res, "workload": args.workload, "tol": args.lbar_tol}),
+              flush=True)
         return
 
     charges = [float(x) for x in w["q"]]

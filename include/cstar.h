@@ -150,6 +150,43 @@ cstar_status q_lowest_eigs(cstar_gauge *g, double m0, int k, const cstar_eig_opt
                            double *resid, void *evecs, cstar_eig_stats *stats);
 
 typedef struct {
+    double tol;              /* stop when the half-width bound <= tol * lambda_bar (0 = 1e-3) */
+    int degree;              /* Chebyshev degree per outer step, <= 64 (0 = 8) */
+    int plain_steps;         /* plain power steps before the Chebyshev steps (0 = 3) */
+    int max_outer;           /* outer steps (0 = 500) */
+    int max_cg;              /* CG iterations per inner solve (0 = 20000) */
+    unsigned long long seed; /* start vector */
+} cstar_lbar_opts;
+
+typedef struct {
+    int outer;               /* outer (power or Chebyshev) steps */
+    int solves;              /* inner CG solves of Q^2 x = y */
+    long cg_iterations;      /* CG iterations over all solves */
+    long applies_fp64;       /* single-RHS D applications, all in FP64 */
+    double beta;             /* final upper end of the damped interval of Q^-2 (0: none used) */
+    double resid_q2;         /* ||Q^2 v - theta v|| of the final unit vector */
+    double seconds;          /* wall time of the call */
+} cstar_lbar_stats;
+
+/*
+ * lambda_bar(m0) = min |lambda(Q(m0))| by the power method with Chebyshev
+ * acceleration applied to Q(m0)^-2, as the paper proposes for step A of the
+ * sign algorithm (Sec. 3: only the smallest eigenvalue of |Q| is needed);
+ * every product with Q^-2 is an FP64 conjugate-gradient solve on Q^2.
+ * lambda_bar: host, sqrt(theta) with theta = v^H Q^2 v the final Rayleigh
+ * quotient (an upper bound of lambda_bar^2).  bound: nullable host, the
+ * half-width of the interval around lambda_bar that holds |lambda| of some
+ * eigenvalue of Q, from r = ||Q^2 v - theta v||:
+ * max(sqrt(theta) - sqrt(theta - r), sqrt(theta + r) - sqrt(theta)).  That it
+ * is the smallest one rests on the iteration's convergence, as in the paper.
+ * opts, stats: nullable.  Allocates 8 FP64 vectors for the call.  Synchronous.
+ * Errors: EINVAL (bad options), ENOCONV (max_outer reached; the outputs hold
+ * the last iterate), ENOMEM, EDEVICE.
+ */
+cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const cstar_lbar_opts *opts, double *lambda_bar,
+                                double *bound, cstar_lbar_stats *stats);
+
+typedef struct {
     cstar_eig_opts eig;  /* eigensolver options for every mass point */
     int k;               /* eigenvalues per mass point (>= 1) */
     double c;            /* step-A factor, slightly below 2 (paper); 0 = 1.9 */

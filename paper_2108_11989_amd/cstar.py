@@ -45,6 +45,17 @@ class EigStats(ctypes.Structure):
                 ("nn_fallback", ctypes.c_int)]
 
 
+class LbarOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("degree", ctypes.c_int), ("plain_steps", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+
+
+class LbarStats(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int), ("solves", ctypes.c_int), ("cg_iterations", ctypes.c_long),
+                ("applies_fp64", ctypes.c_long), ("beta", ctypes.c_double), ("resid_q2", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
 class SignOpts(ctypes.Structure):
     _fields_ = [("eig", EigOpts), ("k", ctypes.c_int), ("c", ctypes.c_double), ("m_max", ctypes.c_double)]
 
@@ -87,6 +98,8 @@ def lib():
         L.dirac_apply.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.q_lowest_eigs.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(EigOpts), dp, dp, vp,
                                     ctypes.POINTER(EigStats)]
+        L.q_lambda_bar_power.argtypes = [vp, ctypes.c_double, ctypes.POINTER(LbarOpts), dp, dp,
+                                         ctypes.POINTER(LbarStats)]
         L.pfaffian_sign.argtypes = [vp, dp, ctypes.c_int, ctypes.POINTER(SignOpts), ip, ctypes.POINTER(SignReport)]
         L.cstar_sign_driver.argtypes = [PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ip, ctypes.POINTER(SignReport)]
@@ -108,7 +121,7 @@ def lib():
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
-                     "q_lowest_eigs", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
+                     "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
                      "cstar_nn_loss_grad", "cstar_nn_adam_step", "cstar_nn_train", "cstar_nn_attach"):
@@ -226,6 +239,20 @@ class Gauge:
         if status != OK and (raise_on_noconv or status != ENOCONV):
             _check(status)
         return ev, res, st
+
+    def lambda_bar_power(self, m0, tol=1e-3, degree=0, plain_steps=0, max_outer=0, max_cg=0, seed=1,
+                         raise_on_noconv=True):
+        """min |lambda(Q(m0))| by the power method with Chebyshev acceleration on Q^-2:
+        (lambda_bar, half-width bound, LbarStats)."""
+        o = LbarOpts(float(tol), int(degree), int(plain_steps), int(max_outer), int(max_cg), int(seed))
+        lam = ctypes.c_double(0.0)
+        bound = ctypes.c_double(0.0)
+        st = LbarStats()
+        status = lib().q_lambda_bar_power(self.h, float(m0), ctypes.byref(o), ctypes.byref(lam), ctypes.byref(bound),
+                                          ctypes.byref(st))
+        if status != OK and (raise_on_noconv or status != ENOCONV):
+            _check(status)
+        return lam.value, bound.value, st
 
     def pfaffian_sign(self, m_path, k=4, c=1.9, m_max=0.0, eig: EigOpts | None = None):
         m = np.ascontiguousarray(np.asarray(m_path, dtype=np.float64))
