@@ -111,3 +111,18 @@ def test_sign_driver_ambiguous_path_point():
 def test_sign_driver_rejects_bad_c():
     st, _, _ = cstar.sign_driver(_provider(np.ones(2), np.ones(2)), [0.0], k=2, c=2.5, m_max=1.0)
     assert st == cstar.EINVAL
+
+
+def test_solvers_reject_null_handle_without_gpu():
+    """Argument checks come before any device call: a null handle is EINVAL, with a message."""
+    L = cstar.lib()
+    lam = ctypes.c_double(0.0)
+    bound = ctypes.c_double(0.0)
+    st = L.q_lambda_bar_power(None, 0.0, None, ctypes.byref(lam), ctypes.byref(bound), None)
+    assert st == cstar.EINVAL
+    assert b"q_lambda_bar_power" in L.cstar_last_error()
+    ev = np.zeros(2)
+    res = np.zeros(2)
+    st = L.q_lowest_eigs(None, 0.0, 2, None, ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None)
+    assert st == cstar.EINVAL
