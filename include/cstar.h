@@ -179,7 +179,8 @@ typedef struct {
  * eigenvalue of Q, from r = ||Q^2 v - theta v||:
  * max(sqrt(theta) - sqrt(theta - r), sqrt(theta + r) - sqrt(theta)).  That it
  * is the smallest one rests on the iteration's convergence, as in the paper.
- * opts, stats: nullable.  Allocates 8 FP64 vectors for the call.  Synchronous.
+ * opts, stats: nullable.  Allocates 8 FP64 vectors on the handle's device and
+ * frees them before it returns.  Synchronous.
  * Errors: EINVAL (bad options), ENOCONV (max_outer reached; the outputs hold
  * the last iterate), ENOMEM, EDEVICE.
  */
