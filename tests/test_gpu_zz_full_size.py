@@ -1,0 +1,84 @@
+"""Full-size parity of the apply at the batched 32^4 workload (32x32^3, eps 0.3,
+seed 2, 10 smoothing steps, q = 2/3), in the launch configuration of the
+eigensolver's inner loop: one multi-RHS launch of the BF16-link form with 12
+right-hand sides, each at its own mass (the first 12 masses of the kappa path).
+
+* Every entry of the first and the last output equals the oracle in its
+  BF16-link emulation mode on the FP32-rounded inputs, max |diff| <= 2e-6
+  max |ref| (FP32 arithmetic over ~100 terms, as on the small lattices).
+* A single-RHS launch of the first input gives the same output bit for bit
+  (the two launches differ only in the cache policy of the clover loads).
+* The FP64 form on the first input equals the exact oracle, <= 1e-13.
+
+Collected last: it holds the most host memory (about 15 GB) and takes about
+a minute, mostly in the host-side oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import dirac as odirac
+from paper_2108_11989_amd import cstar, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NRHS = 12
+
+
+def _relerr(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_apply_32_4_batched_workload_multi_rhs():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    w = synth.WORKLOADS["batched_32^4"]
+    T, L, q = w["T"], w["L"], w["q"][0]
+    print("full size: 32^4 field", flush=True)
+    su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
+    g = cstar.Gauge(su3, th, q, synth.CSW_SU3, synth.CSW_U1)
+    masses = [float(m) for m in synth.kappa_to_m0(w["kappas"][:NRHS])]
+    psi = synth.random_spinor(T, L, 424242, nrhs=NRHS, dtype=np.complex64)
+
+    print("full size: BF16-link launch with 12 right-hand sides", flush=True)
+    prec = cstar.FP32_BF16LINKS
+    canon = torch.from_numpy(psi).cuda().contiguous()
+    nin, nout = g.new_native(NRHS, prec), g.new_native(NRHS, prec)
+    g.pack(canon, nin, prec, NRHS)
+    g.apply(nin, nout, masses, prec, True)
+    res = torch.empty_like(canon)
+    g.unpack(nout, res, prec, NRHS)
+    # the first input alone, single-RHS launch
+    one_in, one_out = g.new_native(1, prec), g.new_native(1, prec)
+    g.pack(canon[:1].contiguous(), one_in, prec, 1)
+    g.apply(one_in, one_out, masses[:1], prec, True)
+    one = torch.empty_like(canon[:1])
+    g.unpack(one_out, one, prec, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(one[0], res[0])
+    picks = {j: res[j].cpu().numpy().astype(np.complex128) for j in (0, NRHS - 1)}
+    del canon, res, one, nin, nout, one_in, one_out
+
+    print("full size: oracle, BF16-link emulation", flush=True)
+    opb = odirac.Operator(su3, th, q, synth.CSW_SU3, synth.CSW_U1, link_mode=2)
+    for j, out in picks.items():
+        ref = opb.apply(psi[j].astype(np.complex128), masses[j], True)
+        err = _relerr(out, ref)
+        print(f"  rhs {j} (m0 {masses[j]:+.4f}): max rel diff {err:.2e}", flush=True)
+        assert err < 2e-6
+    del opb
+
+    print("full size: FP64 form against the exact oracle", flush=True)
+    p64 = psi[0].astype(np.complex128)
+    c64 = torch.from_numpy(p64[None]).cuda().contiguous()
+    n64_in, n64_out = g.new_native(1, cstar.FP64), g.new_native(1, cstar.FP64)
+    g.pack(c64, n64_in, cstar.FP64, 1)
+    g.apply(n64_in, n64_out, masses[:1], cstar.FP64, False)
+    r64 = torch.empty_like(c64)
+    g.unpack(n64_out, r64, cstar.FP64, 1)
+    torch.cuda.synchronize()
+    out64 = r64[0].cpu().numpy()
+    op = odirac.Operator(su3, th, q, synth.CSW_SU3, synth.CSW_U1)
+    err = _relerr(out64, op.apply(p64, masses[0], False))
+    print(f"  FP64: max rel diff {err:.2e}", flush=True)
+    assert err < 1e-13
+    g.close()
