@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the C* Pfaffian-sign hot path on one MI355X.
 
-One step = the whole hot path for one gauge field that is already resident
-in HBM: link packing and the clover term (gauge create from device memory),
-then the sign of the Pfaffian over the kappa path (eigenvalue flow of
-Q = g5 D followed with step A, certified crossing counts; Chebyshev-Davidson
-with FP32/BF16-link filter applies and FP64 Rayleigh-Ritz).
+One step = one block application of the Wilson-clover operator D to 16
+right-hand sides at 16 masses of the kappa path, in the solver's inner form
+(FP32 spinors and arithmetic, BF16-stored links), on the batched 32^4 field,
+in a single launch.  Inputs are resident in HBM before the timed region; the
+launches are timed with HIP events on the handle's stream and the steps with
+the wall clock between device synchronisations.
 
-Printed: ONE JSON line with the throughput in Dirac applies/s (right-hand
-sides applied by every kernel launch of the step, all precisions), the time
-per step (= seconds per Pfaffian sign over the path), the roofline of the
-dominant kernel measured with HIP events around its launches inside the
-timed region, and the CPU oracle timed on a bounded sample.
+After the timed steps, on the same field: the single-RHS apply in every
+precision, the CPU oracle on a bounded sample, and the time to sign over the
+32-point kappa path for the mixed-precision, plain FP64 and learned forms --
+each only while the wall-clock budget allows (skipped legs are named in the
+output).
+
+Printed: ONE JSON line -- RHS-applies/s of the block step, the roofline of
+its kernel (algorithmic bytes over the HIP-event launch time), the CPU oracle
+and the seconds per Pfaffian sign.
 """
 from __future__ import annotations
 
@@ -25,9 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+T_START = time.time()
 
-
-ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources of the apply kernels; the committed counter summary records their hash
 APPLY_SOURCES = ("paper_2108_11989_amd/csrc/kernels_dirac.hip", "paper_2108_11989_amd/csrc/lattice_dev.h")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_traffic_32x32x32x32.md")
@@ -80,15 +84,28 @@ def algorithmic_bytes(prec: int, nsites2: int, launches: int, rhs: int, operands
     return nsites2 * (per_rhs * rhs + shared * launches + per_rhs / 2 * operands)
 
 
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
-    """The oracle's FP64 apply timed on the host cores (bounded sample)."""
+    """The oracle's FP64 apply of Q timed on the host cores (bounded sample).
+    The oracle's setup (field strength and link table, once per operator) is
+    not counted; applies run until about half the budget is spent, at most 20."""
     import numpy as np
 
     from oracle import dirac as odirac
     from paper_2108_11989_amd import synth
-    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     t0 = time.time()
     op = odirac.Operator(su3, th, q)
+    op.links()
     t_setup = time.time() - t0
     psi = synth.random_spinor(T, L, 5)
     n = 0
@@ -100,8 +117,10 @@ def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
         if time.time() - t0 > budget_s * 0.5 or n >= 20:
             break
     dt = time.time() - t0
-    return {"value": n / dt, "unit": "Dirac applies/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3 (clover setup {t_setup:.1f} s not counted)"}
+    return {"value": n / dt, "unit": "Dirac applies/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "threads": threads, "host_cpus": len(os.sched_getaffinity(0)),
+            "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3 (one RHS each; setup of the field strength "
+                      f"and link table, {t_setup:.1f} s, not counted)"}
 
 
 def train_network(args, w, q, m_train):
@@ -265,26 +284,57 @@ def kernel_probe(args, su3_d, th_d, q, T, L):
     print(json.dumps({"kernel_probe": res, "lattice": f"{T}x{L}^3"}), flush=True)
 
 
+def block_step_masses(kappas, nrhs):
+    """nrhs masses spread over the kappa path (every other point of the 32-point path for 16)."""
+    import numpy as np
+
+    from paper_2108_11989_amd import synth
+    idx = np.linspace(0, len(kappas) - 1, nrhs).round().astype(int)
+    return [float(m) for m in synth.kappa_to_m0(np.asarray(kappas)[idx])]
+
+
+def single_rhs_rates(g, nsites2, reps=20):
+    """Single-RHS apply of Q in every precision on the step's field (HIP events)."""
+    from paper_2108_11989_amd import cstar
+    out = {}
+    for prec, name in [(cstar.FP64, "fp64"), (cstar.FP32, "fp32"), (cstar.FP32_BF16LINKS, "fp32_bf16links")]:
+        nin, nout = g.new_native(1, prec), g.new_native(1, prec)
+        nin.normal_()
+        for _ in range(3):
+            g.apply(nin, nout, [-0.3], prec, True)
+        g.timing(True)
+        for _ in range(reps):
+            g.apply(nin, nout, [-0.3], prec, True)
+        tm = g.read_timing()[prec]
+        g.timing(False)
+        ms = tm["ms"] / tm["launches"]
+        gbs = algorithmic_bytes(prec, nsites2, 1, 1) / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "applies_per_s": 1e3 / ms, "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        del nin, nout
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched_32^4")
+    ap.add_argument("--nrhs", type=int, default=16, help="right-hand sides (and masses) of the block step")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget from process start; optional legs that would exceed it are skipped")
+    ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned",
+                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned; 'none')")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=0, help="eigensolver block size (0: 2k + max(8, k))")
-    ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--path-points", type=int, default=0, help="use only the first n kappas (0 = all)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only time the apply kernels on the workload lattice (for profiler runs)")
     ap.add_argument("--probe-reps", type=int, default=20)
     ap.add_argument("--probe-nrhs", type=int, default=0, help="multi-RHS width of the probe (0: the solver block)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run one device copy of this many GiB (counter calibration)")
-    ap.add_argument("--compare-masses", type=int, default=1,
-                    help="learned vs plain: cold eigensolves at the first n path masses after the timed region (0: skip)")
     ap.add_argument("--compare-path", action="store_true",
                     help="learned vs plain over the whole path (three Pfaffian signs; minutes), instead of the timed step")
     ap.add_argument("--compare-lbar", type=int, default=0,
@@ -292,17 +342,20 @@ def main():
                          "instead of the timed step")
     ap.add_argument("--lbar-tol", type=float, default=1e-3, help="relative accuracy of lambda_bar in --compare-lbar")
     ap.add_argument("--lbar-max-outer", type=int, default=100)
+    ap.add_argument("--sign-path", action="store_true",
+                    help="instead of the block step: Pfaffian signs over the path for every charge of the workload "
+                         "(--learned: with the trained preconditioner), timed")
+    ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"], help="filter precision of --sign-path")
+    ap.add_argument("--learned", action="store_true", help="--sign-path with the learned preconditioner")
     ap.add_argument("--charges", default="", help="comma-separated indices of the workload's quark charges (default: all)")
-    ap.add_argument("--learned", action="store_true",
-                    help="timed step with the learned preconditioner (trained before the timed region)")
     ap.add_argument("--train-fields", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(a single lattice or an ensemble would shard by configuration/flavour; see the design notes).",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path in this library "
+              "(an ensemble shards by configuration and flavour with no exchange; a single lattice would be cut "
+              "along t with one halo exchange per apply).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -314,7 +367,7 @@ def main():
         log("no GPU")
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
-    T, L, q = w["T"], w["L"], w["q"][0]  # q: the first charge (comparisons, probes, CPU baseline)
+    T, L, q = w["T"], w["L"], w["q"][0]
     log(f"[bench] workload {args.workload}: {T}x{L}^3, eps {w['eps']}, seed {w['seed']}, smear {w['smear']}")
     t0 = time.time()
     su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
@@ -325,93 +378,114 @@ def main():
         kernel_probe(args, su3_d, th_d, q, T, L)
         return
     kappas = w["kappas"] if args.path_points <= 0 else w["kappas"][: args.path_points]
-    masses = np.asarray(synth.kappa_to_m0(kappas), dtype=np.float64)
-    inner = {"bf16": cstar.FP32_BF16LINKS, "fp32": cstar.FP32, "fp64": cstar.FP64}[args.inner]
-    opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, block=args.block)
+    path = np.asarray(synth.kappa_to_m0(kappas), dtype=np.float64)
     nsites2 = 2 * T * L ** 3
 
     if args.compare_path:
-        net, info = train_network(args, w, q, float(masses[0]))
-        res = compare_forms(args, net, su3_d, th_d, q, masses, True)
+        net, info = train_network(args, w, q, float(path[0]))
+        res = compare_forms(args, net, su3_d, th_d, q, path, True)
         net.close()
         print(json.dumps({"learned_vs_plain_path": res, "train": info, "workload": args.workload,
-                          "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol}), flush=True)
+                          "kappa_points": int(len(path)), "k_pairs": args.k, "eig_tol": args.tol}), flush=True)
         return
-
     if args.compare_lbar > 0:
-        res = compare_lambda_bar(args, su3_d, th_d, q, masses[:args.compare_lbar])
+        res = compare_lambda_bar(args, su3_d, th_d, q, path[:args.compare_lbar])
         print(json.dumps({"lambda_bar_power_vs_block": res, "workload": args.workload, "tol": args.lbar_tol}),
               flush=True)
         return
+    if args.sign_path:
+        sign_path(args, w, su3_d, th_d, path, nsites2)
+        return
 
-    charges = [float(x) for x in w["q"]]
-    if args.charges:
-        charges = [charges[int(i)] for i in args.charges.split(",")]
-    net_timed = None
-    if args.learned:
-        net_timed, _ = train_network(args, w, q, float(masses[0]))
-        opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, use_nn=1, block=args.block)
-
-    def step():
-        """One Pfaffian sign over the whole path for every quark charge of the workload."""
-        out = []
-        for qc in charges:
-            g = cstar.Gauge(su3_d, th_d, qc, synth.CSW_SU3, synth.CSW_U1)
-            if net_timed is not None:
-                net_timed.attach(g)
-            g.timing(True)
-            tq = time.perf_counter()
-            signs, rep = g.pfaffian_sign(masses, k=args.k, eig=opts)
-            out.append((signs, rep, g.read_timing()))
-            g.close()
-            log(f"[bench]   q = {qc:+.4f}: {time.perf_counter() - tq:.1f} s, {rep.n_points} mass points, {rep.applies} applies, "
-                f"crossings {rep.n_crossings}, signs {''.join('+' if v > 0 else '-' for v in signs)}")
-        return out
-
-    for i in range(args.warmup):
-        t0 = time.time()
-        step()
-        log(f"[bench] warmup {i}: {time.time() - t0:.2f} s")
+    # ---------------------------------------------------------------- the timed block step
+    prec = cstar.FP32_BF16LINKS
+    g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+    masses = block_step_masses(kappas, args.nrhs)
+    nin, nout = g.new_native(args.nrhs, prec), g.new_native(args.nrhs, prec)
+    torch.manual_seed(0)
+    nin.normal_()
+    log(f"[bench] block step: {args.nrhs} right-hand sides at masses {masses[0]:+.4f} .. {masses[-1]:+.4f}")
+    for _ in range(args.warmup):
+        g.apply(nin, nout, masses, prec, False)
     torch.cuda.synchronize()
+    g.timing(True)
     t0 = time.perf_counter()
-    applies = 0
-    tms = []
-    for i in range(args.steps):
-        res = step()
-        for signs, rep, tm in res:
-            applies += rep.applies
-            tms.append(tm)
-        log(f"[bench] step {i} done")
+    for _ in range(args.steps):
+        g.apply(nin, nout, masses, prec, False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    tm = g.read_timing()[prec]
+    g.timing(False)
+    avg_ms = tm["ms"] / max(tm["launches"], 1)
+    byts = algorithmic_bytes(prec, nsites2, 1, args.nrhs)
+    achieved = byts / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic("bf16", args.nrhs) if args.workload == "batched_32^4" else None
+    log(f"[bench] {args.steps} steps in {dt * 1e3:.2f} ms; kernel {avg_ms:.3f} ms per launch (HIP events), "
+        f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
+    del nin, nout
 
-    # dominant kernel: the precision with the most kernel time
-    ms = [sum(t[p]["ms"] for t in tms) for p in range(3)]
-    dom = int(np.argmax(ms))
-    launches = sum(t[dom]["launches"] for t in tms)
-    rhs = sum(t[dom]["rhs"] for t in tms)
-    operands = sum(t[dom]["operands"] for t in tms)
-    byts = algorithmic_bytes(dom, nsites2, launches, rhs, operands)
-    achieved = byts / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
-    kern_name = {0: "apply FP64", 1: "apply FP32", 2: "apply FP32/BF16-links"}[dom]
-    log(f"[bench] kernel time by precision (ms): {ms}; dominant {kern_name}: {launches} launches, "
-        f"{rhs} rhs, avg {ms[dom] / max(launches, 1):.3f} ms/launch, {achieved:.0f} GB/s")
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
+    skipped = []
 
-    compare = None
-    if args.compare_masses > 0:
-        net, info = train_network(args, w, q, float(masses[0]))
-        compare = {"train": info, "forms": compare_forms(args, net, su3_d, th_d, q, masses[:args.compare_masses],
-                                                         False)}
-        net.close()
+    def have(est_s, name):
+        left = args.budget_s - (time.time() - T_START)
+        if est_s > left:
+            skipped.append(f"{name} (estimated {est_s:.0f} s, {max(left, 0):.0f} s of budget left)")
+            log(f"[bench] skipping {name}: estimated {est_s:.0f} s, {left:.0f} s left")
+            return False
+        return True
+
+    single = None
+    if "single" in legs and have(5, "single"):
+        single = single_rhs_rates(g, nsites2)
+        for k_, v in single.items():
+            log(f"[bench] single RHS {k_}: {v['ms']:.3f} ms, {v['GBs']:.0f} GB/s ({100 * v['frac']:.1f} %)")
+    g.close()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if "cpu" in legs and have(60, "cpu"):
         log("[bench] timing the CPU oracle")
         cpu = cpu_baseline(su3, th, q, T, L)
+        log(f"[bench] CPU oracle: {cpu['value']:.2f} applies/s on {cpu['threads']} threads ({cpu['cpu_model']})")
+
+    # ---------------------------------------------------------------- time to sign, three forms
+    signs = {}
+    inner = {"bf16": cstar.FP32_BF16LINKS, "fp64": cstar.FP64}
+
+    def one_sign(name, form, net=None):
+        gg = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+        if net is not None:
+            net.attach(gg)
+        opts = cstar.eig_opts(inner=inner[form], tol=args.tol, max_iter=1000, use_nn=int(net is not None),
+                              block=args.block)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sg, rep = gg.pfaffian_sign(path, k=args.k, eig=opts)
+        s_ = time.perf_counter() - t1
+        gg.close()
+        signs[name] = {"s_per_sign": s_, "applies": rep.applies, "mass_points_solved": rep.n_points,
+                       "crossings": rep.n_crossings, "nn_applies": rep.nn_applies, "nn_fallbacks": rep.nn_fallbacks,
+                       "signs": "".join("+" if v > 0 else "-" for v in sg)}
+        log(f"[bench] sign {name}: {s_:.1f} s, {rep.n_points} points solved, {rep.applies} applies, "
+            f"signs {signs[name]['signs']}")
+        return s_
+
+    s_mixed = 60.0
+    if "mixed" in legs and have(90, "sign mixed"):
+        s_mixed = one_sign("mixed", "bf16")
+    if "fp64" in legs and have(2.2 * s_mixed + 10, "sign plain_fp64"):
+        one_sign("plain_fp64", "fp64")
+    if "learned" in legs and have(1.4 * s_mixed + 40, "sign learned_mixed"):
+        net, info = train_network(args, w, q, float(path[0]))
+        one_sign("learned_mixed", "bf16", net)
+        signs["learned_mixed"]["train"] = info
+        net.close()
+    if len({v["signs"] for v in signs.values()}) > 1:
+        log("[bench] WARNING: the forms disagree on the signs")
 
     out = {
         "metric": "Dirac applies/s & HBM GB/s (% peak) at 32^4; s per Pfaffian sign, learned vs plain",
-        "value": applies / dt,
+        "value": args.nrhs * args.steps / dt,
         "unit": "Dirac applies/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -420,24 +494,74 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16": "fp32+bf16-links/f64", "fp32": "f32/f64", "fp64": "f64"}[args.inner],
+        "dtype": "fp32 (bf16-stored links)",
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": f"{T}x{L}^3", "sites_doubled": nsites2,
-                   "kappa_points": int(len(masses)), "k_pairs": args.k, "eig_tol": args.tol,
-                   "inner": args.inner, "learned": bool(args.learned), "charges": charges, "s_per_sign": dt / args.steps / len(charges),
-                   "mass_points_solved": [r.n_points for _, r, _ in res],
-                   "crossings": [r.n_crossings for _, r, _ in res],
-                   "signs": ["".join("+" if v > 0 else "-" for v in sg) for sg, _, _ in res]},
-        "roofline": {"bound": "hbm", "kernel": kern_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic({0: "fp64", 1: "fp32", 2: "bf16"}[dom], rhs / max(launches, 1))
-                                 if args.workload == "batched_32^4" else None),
-                     "algorithmic_bytes_per_launch": byts / max(launches, 1),
-                     "avg_launch_ms": ms[dom] / max(launches, 1), "rhs_per_launch": rhs / max(launches, 1)},
+                   "step": f"one launch: D applied to {args.nrhs} right-hand sides at {args.nrhs} masses",
+                   "nrhs": args.nrhs, "masses": masses, "charge": q,
+                   "sign_path": {"kappa_points": int(len(path)), "k_pairs": args.k, "eig_tol": args.tol}},
+        "roofline": {"bound": "hbm", "kernel": "k_apply_march (FP32, BF16 links, multi-RHS)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": byts, "avg_launch_ms": avg_ms},
         "cpu_baseline": cpu,
-        "learned_vs_plain": compare,
+        "single_rhs": single,
+        "s_per_sign": {k_: v["s_per_sign"] for k_, v in signs.items()},
+        "signs": signs,
+        "signs_agree": len({v["signs"] for v in signs.values()}) <= 1,
+        "skipped": skipped,
+        "wall_s": time.time() - T_START,
     }
     print(json.dumps(out), flush=True)
+
+
+def sign_path(args, w, su3_d, th_d, path, nsites2):
+    """Pfaffian signs over the path for every charge of the workload, timed
+    (profiling and paper-scale runs)."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    inner = {"bf16": cstar.FP32_BF16LINKS, "fp32": cstar.FP32, "fp64": cstar.FP64}[args.inner]
+    charges = [float(x) for x in w["q"]]
+    if args.charges:
+        charges = [charges[int(i)] for i in args.charges.split(",")]
+    net = None
+    opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, block=args.block)
+    if args.learned:
+        net, _ = train_network(args, w, charges[0], float(path[0]))
+        opts = cstar.eig_opts(inner=inner, tol=args.tol, max_iter=1000, use_nn=1, block=args.block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for qc in charges:
+        g = cstar.Gauge(su3_d, th_d, qc, synth.CSW_SU3, synth.CSW_U1)
+        if net is not None:
+            net.attach(g)
+        g.timing(True)
+        tq = time.perf_counter()
+        sg, rep = g.pfaffian_sign(path, k=args.k, eig=opts)
+        tm = g.read_timing()
+        g.close()
+        res.append({"q": qc, "s": time.perf_counter() - tq, "mass_points_solved": rep.n_points,
+                    "applies": rep.applies, "crossings": rep.n_crossings,
+                    "signs": "".join("+" if v > 0 else "-" for v in sg), "timing": tm})
+        log(f"[bench] q = {qc:+.4f}: {res[-1]['s']:.1f} s, {rep.n_points} points, {rep.applies} applies, "
+            f"signs {res[-1]['signs']}")
+    dt = time.perf_counter() - t0
+    ms = [sum(r["timing"][p]["ms"] for r in res) for p in range(3)]
+    dom = int(np.argmax(ms))
+    launches = sum(r["timing"][dom]["launches"] for r in res)
+    rhs = sum(r["timing"][dom]["rhs"] for r in res)
+    operands = sum(r["timing"][dom]["operands"] for r in res)
+    byts = algorithmic_bytes(dom, nsites2, launches, rhs, operands)
+    achieved = byts / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
+    for r in res:
+        del r["timing"]
+    print(json.dumps({"sign_path": res, "workload": args.workload, "inner": args.inner, "learned": args.learned,
+                      "s_total": dt, "applies_per_s": sum(r["applies"] for r in res) / dt,
+                      "dominant_kernel": {"prec": dom, "launches": launches, "rhs_per_launch": rhs / max(launches, 1),
+                                          "avg_ms": ms[dom] / max(launches, 1), "GBs": achieved,
+                                          "frac": achieved / HBM_PEAK_GBS}}), flush=True)
 
 
 if __name__ == "__main__":

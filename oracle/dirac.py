@@ -41,6 +41,9 @@ def lib():
                                             ctypes.c_double, ctypes.c_double, dp]
         L.oracle_dirac.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                    dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_links.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_int, dp]
+        L.oracle_dirac_tab.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double,
+                                       ctypes.c_int, dp, dp]
         L.oracle_gammas.argtypes = [dp]
         L.oracle_neighbours.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
         L.oracle_transport.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
@@ -78,6 +81,7 @@ class Operator:
         self.q, self.csw_su3, self.csw_u1 = float(q), float(csw_su3), float(csw_u1)
         self.time_bc, self.link_mode = int(time_bc), int(link_mode)
         self.nsites = 2 * self.T * self.L ** 3
+        self._V = None
         self.F = None
         if clover:
             self.F = np.zeros((self.nsites, 6, 3, 3), dtype=np.complex128)
@@ -92,14 +96,23 @@ class Operator:
     def dim(self):
         return self.nsites * 12
 
+    def links(self) -> np.ndarray:
+        """The quark link table the operator uses, complex [2V][4][3][3] on the
+        doubled lattice (built once per operator, in its link_mode)."""
+        if self._V is None:
+            V = np.empty((self.nsites, 4, 3, 3), dtype=np.complex128)
+            lib().oracle_links(self.T, self.L, self.q, _p(self.su3), _p(self.theta), self.link_mode, _p(V))
+            self._V = V
+        return self._V
+
     def apply(self, psi: np.ndarray, m0: float, gamma5: bool = False) -> np.ndarray:
         psi = np.ascontiguousarray(psi, dtype=np.complex128)
         if psi.size != self.dim:
             raise ValueError("spinor size mismatch")
         out = np.empty_like(psi)
         F = _p(self.F) if self.F is not None else None
-        rc = lib().oracle_dirac(self.T, self.L, self.time_bc, self.q, _p(self.su3), _p(self.theta), F,
-                                float(m0), int(bool(gamma5)), self.link_mode, _p(psi), _p(out))
+        rc = lib().oracle_dirac_tab(self.T, self.L, self.time_bc, _p(self.links()), F, float(m0),
+                                    int(bool(gamma5)), _p(psi), _p(out))
         if rc != 0:
             raise MemoryError("oracle_dirac failed")
         return out

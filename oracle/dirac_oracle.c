@@ -292,18 +292,27 @@ static void build_links(const geom *g, const double *su3, const double *theta, d
 }
 
 /*
- * out = D(m0) in   (gamma5 != 0: out = gamma5 D(m0) in).
- * F: field strength from oracle_field_strength (NULL: no clover term).
- * in/out: [2V][4][3] complex double, non-aliasing.
+ * The quark link table as the operator uses it, for the oracle's own pins:
+ * Vtab_out[site][mu][3][3] complex double on the doubled lattice (link_mode
+ * as in build_links).
  */
-int oracle_dirac(int T, int L, int time_bc, double q, const double *su3, const double *theta,
-                 const double *F, double m0, int gamma5, int link_mode, const double *in, double *out) {
+int oracle_links(int T, int L, double q, const double *su3, const double *theta, int link_mode, double *Vtab_out) {
+    geom g = {T, L, 1};
+    build_links(&g, su3, theta, q, link_mode, (cplx *)Vtab_out);
+    return 0;
+}
+
+/*
+ * out = D(m0) in   (gamma5 != 0: out = gamma5 D(m0) in) with a link table
+ * from oracle_links.  F: field strength from oracle_field_strength (NULL: no
+ * clover term).  in/out: [2V][4][3] complex double, non-aliasing.
+ */
+int oracle_dirac_tab(int T, int L, int time_bc, const double *Vtab_in, const double *F, double m0, int gamma5,
+                     const double *in, double *out) {
     init_gamma();
     geom g = {T, L, time_bc};
     long n = n_sites(&g);
-    cplx *Vtab = (cplx *)malloc(sizeof(cplx) * n * 36);
-    if (!Vtab) return -2;
-    build_links(&g, su3, theta, q, link_mode, Vtab);
+    const cplx *Vtab = (const cplx *)Vtab_in;
     const cplx *psi = (const cplx *)in;
     cplx *res = (cplx *)out;
     static const int planes[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
@@ -383,8 +392,20 @@ int oracle_dirac(int T, int L, int time_bc, double q, const double *su3, const d
                 res[s * 12 + a * 3 + i] = v;
             }
     }
-    free(Vtab);
     return 0;
+}
+
+/* As oracle_dirac_tab, building the link table for this call. */
+int oracle_dirac(int T, int L, int time_bc, double q, const double *su3, const double *theta,
+                 const double *F, double m0, int gamma5, int link_mode, const double *in, double *out) {
+    geom g = {T, L, time_bc};
+    long n = n_sites(&g);
+    cplx *Vtab = (cplx *)malloc(sizeof(cplx) * n * 36);
+    if (!Vtab) return -2;
+    build_links(&g, su3, theta, q, link_mode, Vtab);
+    int rc = oracle_dirac_tab(T, L, time_bc, (const double *)Vtab, F, m0, gamma5, in, out);
+    free(Vtab);
+    return rc;
 }
 
 /* Gamma matrices as used above (for the oracle's own self-tests):

@@ -562,12 +562,14 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
         std::sort(ord.begin(), ord.end(), [&](int a, int b) { return lq[a] < lq[b]; });
         struct Pr { double lam, err; int a; };
         std::vector<Pr> prs;
+        std::vector<char> paired(nq, 0);
         const double qscale = std::sqrt(bup);
         for (int i = 0; i + 1 < nq;) {
             const int a = ord[i], b = ord[i + 1];
             const double gap = std::fabs(lq[a] - lq[b]);
             if (gap <= 2.0 * (rn[a] + rn[b]) + 1e-13 * qscale) {
                 prs.push_back({0.5 * (lq[a] + lq[b]), std::max(rn[a], rn[b]) + 0.5 * gap, a});
+                paired[a] = paired[b] = 1;
                 i += 2;
             } else {
                 i += 1;
@@ -593,7 +595,17 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             fprintf(stderr, "[cstar eig] m=%.6f it=%d nb=%d nq=%d ny=%d deg=%d pairs=%zu filter=%s acut=%.3e rmax=%.3e lam0=%.6e res0=%.2e\n",
                     m0, it, nb, nq, ny, deg, prs.size(), fp64_filter ? "fp64" : (inner == CSTAR_FP32 ? "fp32" : "bf16"), acut, rmax, prs.empty() ? 0.0 : prs[0].lam,
                     prs.empty() ? 0.0 : prs[0].err);
-        // a wanted pair must also be separated from the unpaired / guard Ritz values
+        // Completeness of the list: a signed Ritz value without a Kramers partner
+        // whose error interval reaches down into the wanted range may be a low
+        // mode not yet resolved (its partner still outside the subspace), so the
+        // k listed pairs are not yet known to be the lowest: keep iterating.
+        int unpaired_low = 0;
+        if (ok) {
+            const double reach = std::fabs(lam_out[k - 1]) + res_out[k - 1];
+            for (int j = 0; j < nq; j++)
+                if (!paired[j] && std::fabs(lq[j]) - rn[j] <= reach) unpaired_low++;
+            if (unpaired_low) ok = false;
+        }
         if (ok) {
             converged = true;
             if (evecs) {
@@ -615,6 +627,28 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
         for (int i = 0; i < k && i < (int)prs.size(); i++) rabs = std::max(rabs, prs[i].err);
         if ((int)prs.size() < k) rabs = 1e300;
         stall = (rabs > 0.8 * last_rabs) ? stall + 1 : 0;
+        // last rung: the FP64 filter converges geometrically while the block
+        // resolves the wanted pairs; eight iterations without a 0.8 reduction
+        // mean it does not (e.g. a multiplet of A wider than the block), so the
+        // call ends with ENOCONV instead of raising the degree further
+        if (fp64_filter && stall >= 8) {
+            CSTAR_HIP(hipStreamSynchronize(c.s));
+            for (int i = 0; i < k; i++) {
+                evals[i] = lam_out[i];
+                if (resid) resid[i] = res_out[i];
+            }
+            if (stats) {
+                stats->iterations = it + 1;
+                stats->applies_fp64 = c.ap64;
+                stats->applies_inner = c.ap_inner;
+                stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+                stats->lambda_max_est = bup;
+                stats->nn_applies = c.nn_applies;
+                stats->nn_fallback = 0;
+            }
+            return fail(CSTAR_ENOCONV, "q_lowest_eigs: no progress in the FP64 filter (the block may be smaller "
+                                       "than a multiplet of Q^2 at the wanted end; raise opts.block)");
+        }
         if (rmax < 1e-4) refine = true;
         if (!fp64_filter && stall >= 3) {
             if (inner == CSTAR_FP32_BF16LINKS)

@@ -12,7 +12,8 @@
 // point; then the segments between solved masses are certified:
 // A segment [a,b] of solved masses is certified
 //   (i)  crossing-free when the exclusion intervals of a and b cover it:
-//        (lambda_bar(a) - err_a) + (lambda_bar(b) - err_b) > b - a;
+//        r(a) + r(b) > b - a with r = min_j (|lambda_j| - err_j), a rigorous
+//        lower bound of lambda_bar;
 //   (ii) otherwise by counting: choose a level g < 0 that no eigenvalue can pass
 //        on [a,b] -- every computed eigenvalue at a and b lies farther than
 //        (b-a) + err from g, and |g| + (b-a) + err is inside the radius where
@@ -41,6 +42,7 @@ struct Point {
     double m = 0;
     std::vector<double> ev, err;
     double lb = 0, lb_err = 0;  // lambda_bar and its error bound
+    double excl = 0;            // rigorous lower bound of lambda_bar: min_j (|lambda_j| - err_j), >= 0
     double R = 0;               // completeness radius of the list
     double emax = 0;            // largest error bound
     bool amb = false;           // an eigenvalue within its error of zero
@@ -68,6 +70,12 @@ bool solve_point(cstar_eig_provider prov, void *ctx, double m, int k, Point &p) 
     }
     p.emax = eamax;
     p.R = amax - eamax;
+    // every eigenvalue of Q(m) lies within err_j of a listed one or beyond the
+    // list's reach, so no |lambda| is below min_j (|lambda_j| - err_j): the
+    // exclusion interval uses that, not the error of the smallest |lambda_j|
+    p.excl = 1e300;
+    for (int i = 0; i < k; i++) p.excl = std::min(p.excl, std::fabs(p.ev[i]) - p.err[i]);
+    p.excl = std::max(0.0, std::min(p.excl, p.R));
     return true;
 }
 
@@ -135,7 +143,7 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
         double cur = m_max;
         while (cur > target) {
             const Point &p = pts[cur];
-            const double step = p.amb ? 0.0 : c * std::max(p.lb - p.lb_err, 0.0);
+            const double step = p.amb ? 0.0 : c * p.excl;
             double mnew = cur - step;
             // near a crossing the steps shrink geometrically: leave the rest of
             // the way to the segment certification (midpoint splits)
@@ -159,7 +167,7 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             const Point &a = it->second, &b = std::next(it)->second;
             if (seg_cross.count(a.m)) continue;
             const double D = b.m - a.m;
-            if (!a.amb && !b.amb && (a.lb - a.lb_err) + (b.lb - b.lb_err) > D) {
+            if (!a.amb && !b.amb && a.excl + b.excl > D) {
                 seg_cross[a.m] = 0;
                 seg_excl[a.m] = true;
                 continue;
@@ -175,7 +183,7 @@ cstar_status sign_driver(cstar_eig_provider prov, void *ctx, const double *m_pat
             // shrinks until rule (ii) applies)
             double mnew = 0.5 * (a.m + b.m);
             if (!a.amb) {
-                const double step = c * std::max(a.lb - a.lb_err, 0.0);
+                const double step = c * a.excl;
                 if (step >= 0.25 * D && a.m + step < b.m) mnew = a.m + step;
             }
             if (D < 1e-12 * std::max(1.0, std::fabs(a.m))) {

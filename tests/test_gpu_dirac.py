@@ -73,7 +73,7 @@ def test_fp64_apply_matches_oracle(case, gamma5):
     g.close()
 
 
-@pytest.mark.parametrize("case", CASES[:4] + CASES[5:])
+@pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("prec,mode", [(cstar.FP32, 1), (cstar.FP32_BF16LINKS, 2)])
 def test_fp32_forms_match_emulating_oracle(case, prec, mode):
     _setup()

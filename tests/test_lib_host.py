@@ -126,3 +126,32 @@ def test_solvers_reject_null_handle_without_gpu():
     st = L.q_lowest_eigs(None, 0.0, 2, None, ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None)
     assert st == cstar.EINVAL
+
+
+def test_sign_driver_exclusion_radius_uses_every_error_bound():
+    """The exclusion interval of a solved mass is min_j (|lambda_j| - err_j), not
+    lambda_bar minus the error of the smallest |lambda_j|.  Flow B is a V,
+    lambda_B(m) = |m - 1| - 0.1 (crossings at 0.9 and 1.1), reported 0.5 too
+    high with error bound 0.5 + 1e-9 (a rigorous but loose bound); flow A is a
+    constant 0.6 with a tight bound.  With the radius from A alone (0.6 at 0.6
+    and at 1.5) the segment [0.6, 1.5] would count as crossing-free and the path
+    point m = 1 would get the sign of m = 1.5; the rigorous radii (0.3 and 0.4)
+    do not cover it, so the driver must either find the sign (-1) or report the
+    point as undecidable -- never +1."""
+
+    def prov(m, k):
+        lam_b = abs(m - 1.0) - 0.1
+        ev = np.array([0.6, lam_b + 0.5, 3.0 + m, -4.0 - m])
+        err = np.array([1e-12, 0.5 + 1e-9, 1e-12, 1e-12])
+        order = np.lexsort((ev, np.abs(ev)))[:k]
+        return ev[order], err[order]
+
+    st, signs, rep = cstar.sign_driver(prov, [0.6, 1.0, 1.4], k=4, c=1.9, m_max=1.5)
+    assert st in (cstar.OK, cstar.EAMBIG)
+    assert signs[1] != 1
+    if st == cstar.OK:
+        assert signs[1] == -1
+    # the first step from m_max uses the rigorous radius: 1.5 - 1.9 * min(0.6, 0.9 - 0.5) = 0.74
+    # (with the radius of flow A alone it would jump past the target to 0.6)
+    ms = np.array(rep.m[: rep.n_points])
+    assert np.isclose(ms[0], 1.5) and np.isclose(ms[1], 0.74)

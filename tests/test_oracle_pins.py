@@ -362,39 +362,200 @@ def test_negative_sign_exists_and_agrees():
 
 
 # ----------------------------------------------------------------- quantised links
-def test_bf16_rounding_matches_library():
+# Reading of the compressed link formats: rows 0 and 1 of the physical SU(3)
+# link rounded FP64 -> FP32 (link mode 1) or FP64 -> FP32 -> BF16 with
+# round-to-nearest-even (link mode 2), row 2 rebuilt as conj(row0 x row1) of
+# the rounded rows, the quark phase exp(i q theta) as FP32 cosine and sine;
+# the conjugate copy at x1 + L holds the complex conjugate.  Each pin compares
+# the oracle's link table with an independent conversion (torch for BF16,
+# numpy for FP32) element by element.
+
+def _split_copies(V, T, L):
+    Vs = V.reshape(T, 2 * L, L, L, 4, 3, 3)
+    return Vs[:, :L], Vs[:, L:]
+
+
+def _bf16_ref(x):
     import torch
-    rng = np.random.default_rng(0)
-    x = rng.standard_normal(1000)
-    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
-    # free field + a bf16-exact field: quantised operator equals the exact one
+    return torch.tensor(x, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _tie_values():
+    """FP32 values exactly halfway between two BF16 numbers (low 16 bits 0x8000),
+    with the kept last bit even (RNE rounds down) and odd (RNE rounds up), both
+    signs; and FP64 values just above such a tie that round to it in FP32."""
+    bits = []
+    for hi in (0x3F80, 0x3F81, 0x3E4C, 0x3E4D, 0x3F7F, 0x3C23, 0x3C24):
+        bits.append((hi << 16) | 0x8000)
+        bits.append(((hi | 0x8000) << 16) | 0x8000)
+    f = np.array(bits, dtype=np.uint32).view(np.float32).astype(np.float64)
+    eps32 = np.abs(f) * 2.0 ** -26  # below half an FP32 ulp: rounds to the tie in FP32
+    return np.concatenate([f, f + np.sign(f) * eps32])
+
+
+def _quant_field(T, L, seed, plant_ties):
+    rng = np.random.default_rng(seed)
+    su3 = rng.standard_normal((T, L, L, L, 4, 3, 3)) + 1j * rng.standard_normal((T, L, L, L, 4, 3, 3))
+    su3 *= 0.6
+    if plant_ties:
+        t = _tie_values()
+        flat = su3[..., :2, :].reshape(-1)  # rows 0 and 1 only are stored
+        flat[: t.size] = t + 1j * t[::-1]
+        su3[..., :2, :] = flat.reshape(su3[..., :2, :].shape)
+    return su3
+
+
+def test_bf16_tie_fixture_exercises_both_rounding_directions():
+    """The planted ties: RNE rounds some down and some up, so a truncating or
+    round-half-up conversion disagrees with the reference on them."""
+    t = _tie_values()
+    ref = _bf16_ref(t)
+    f32 = t.astype(np.float32)
+    trunc = (f32.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    half_up = ((f32.view(np.uint32) + np.uint32(0x8000)) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    assert np.any(ref != trunc) and np.any(ref == trunc)
+    assert np.any(ref != half_up) and np.any(ref == half_up)
+    # the values just above a tie round like the tie itself (FP64 -> FP32 first)
+    n = t.size // 2
+    assert np.array_equal(ref[:n], ref[n:])
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_compressed_link_rows_elementwise(mode):
+    """Rows 0 and 1 of the oracle's link table equal an independent rounding of
+    the input rows, bit for bit (theta = 0, so the phase is exactly 1)."""
+    T, L = 2, 2
+    su3 = _quant_field(T, L, 3, plant_ties=True)
+    th = np.zeros((T, L, L, L, 4))
+    op = dirac.Operator(su3, th, 2 / 3, clover=False, link_mode=mode)
+    phys, mirr = _split_copies(op.links(), T, L)
+    src = su3[..., :2, :]
+    if mode == 1:
+        ref = src.real.astype(np.float32).astype(np.float64) + 1j * src.imag.astype(np.float32).astype(np.float64)
+    else:
+        ref = _bf16_ref(src.real) + 1j * _bf16_ref(src.imag)
+    assert np.array_equal(phys[..., :2, :], ref)
+    assert np.array_equal(mirr, phys.conj())
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_compressed_link_third_row(mode):
+    """Row 2 = conj(row0 x row1) of the rounded rows (not of the unrounded input)."""
+    T, L = 2, 2
+    su3 = _quant_field(T, L, 4, plant_ties=False)
+    th = np.zeros((T, L, L, L, 4))
+    op = dirac.Operator(su3, th, 2 / 3, clover=False, link_mode=mode)
+    phys, _ = _split_copies(op.links(), T, L)
+    r0, r1 = phys[..., 0, :], phys[..., 1, :]
+    ref = np.cross(r0, r1).conj()
+    assert np.abs(phys[..., 2, :] - ref).max() <= 1e-15 * np.abs(ref).max()
+    # the rebuilt row is not the input's third row (the input is not unitary)
+    assert np.abs(phys[..., 2, :] - su3[..., 2, :]).max() > 0.1
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_link_phase_and_mirror(mode):
+    """Quark phase exp(i q theta): FP64 in the exact mode, FP32 cosine and sine
+    in the compressed modes; the conjugate copy carries conj(V)."""
+    T, L, q = 2, 2, -1 / 3
+    rng = np.random.default_rng(8)
+    su3 = _quant_field(T, L, 5, plant_ties=False)
+    # rows chosen exactly representable in BF16, so the rows contribute no rounding
+    su3 = _bf16_ref(su3.real) + 1j * _bf16_ref(su3.imag)
+    th = rng.uniform(-3, 3, (T, L, L, L, 4))
+    op = dirac.Operator(su3, th, q, clover=False, link_mode=mode)
+    phys, mirr = _split_copies(op.links(), T, L)
+    if mode == 0:
+        ref = np.exp(1j * q * th)[..., None, None] * su3
+        assert np.abs(phys - ref).max() <= 4e-16 * np.abs(ref).max()
+    else:
+        ph = np.cos(q * th).astype(np.float32).astype(np.float64) + 1j * np.sin(q * th).astype(np.float32).astype(
+            np.float64)
+        r = su3[..., :2, :]
+        assert np.abs(phys[..., :2, :] - ph[..., None, None] * r).max() <= 1e-15
+        # the phase of every entry is within one FP32 rounding of exp(i q theta)
+        ex = np.exp(1j * q * th)[..., None, None] * r
+        assert np.abs(phys[..., :2, :] - ex).max() <= 2 * 2.0 ** -24 * np.abs(r).max() * np.sqrt(2)
+    assert np.abs(mirr - phys.conj()).max() <= 4e-16 * np.abs(phys).max()
+
+
+def test_quantised_operator_uses_its_link_table():
+    """The compressed-mode operator equals the exact-arithmetic hopping built from
+    the rounded table: on the free field (all entries representable) it is the
+    exact operator, on a general field it differs by O(2^-9) per link."""
     T, L = 2, 2
     su3, th = synth.unit_field(T, L)
     op0 = dirac.Operator(su3, th, 2 / 3, CSW, CU1, link_mode=0)
     op2 = dirac.Operator(su3, th, 2 / 3, CSW, CU1, link_mode=2)
     v = synth.random_spinor(T, L, 1)
     assert np.abs(op0.D(v, 0.1) - op2.D(v, 0.1)).max() < 1e-15
-    # a general field: the quantised operator differs by O(2^-9) per link
     su3, th = _field(4, 2, 0.3, 0)
     opq = dirac.Operator(su3, th, 2 / 3, CSW, CU1, link_mode=2)
     ope = dirac.Operator(su3, th, 2 / 3, CSW, CU1, link_mode=0)
     v = synth.random_spinor(4, 2, 2)
     d = np.linalg.norm(opq.D(v, 0.1) - ope.D(v, 0.1)) / np.linalg.norm(v)
     assert 1e-5 < d < 8 * 2 ** -8
-    assert np.max(np.abs(ref - x)) <= 2 ** -8 * np.max(np.abs(x))
 
 
-def test_step_a_on_synthetic_flow():
-    """Step A on a closed-form flow lambda(m) = min_i |a_i + s_i m|."""
-    a = np.array([-0.05, 0.3, -0.8])
-    s = np.array([1.0, 0.6, -0.4])
+# ----------------------------------------------------------------- step A
+# Step A (sign section): from the target mass, m <- m + c lambda_bar(m); stop
+# with "B" as soon as lambda_bar is smaller than at the previous point, with
+# "W=1" once m exceeds m_max.  Flows with closed-form step sequences.
+
+def test_step_a_linear_flow_reaches_m_max():
+    """lambda_bar(m) = m - m_c (one eigenvalue that crossed below the target):
+    m_n - m_c = (1+c)^n (m_0 - m_c), increasing, so step A runs to m_max."""
+    m_c, m0, c, m_max = -0.4, -0.3, 1.9, 2.0
+    out, trace = sign.step_a(lambda m: m - m_c, m0, c, m_max)
+    n_expect = int(np.ceil(np.log((m_max - m_c) / (m0 - m_c)) / np.log(1 + c)))
+    assert out == "W=1"
+    assert len(trace) == n_expect + 1
+    for n, (m, lb) in enumerate(trace):
+        assert abs(m - (m_c + (1 + c) ** n * (m0 - m_c))) < 1e-12
+        assert abs(lb - (m - m_c)) < 1e-12
+    assert trace[-2][0] <= m_max < trace[-1][0]
+
+
+def test_step_a_crossing_above_target_stops_with_b():
+    """lambda_bar(m) = |m - m_x| with m_x above the target: the first step
+    overshoots m_x (c > 1), lambda_bar falls to (c-1)(m_x - m_0) -> step B."""
+    m_x, m0, c = 0.5, 0.2, 1.9
+    out, trace = sign.step_a(lambda m: abs(m - m_x), m0, c, 10.0)
+    assert out == "B"
+    assert len(trace) == 2
+    assert abs(trace[1][0] - (m0 + c * (m_x - m0))) < 1e-15
+    assert abs(trace[1][1] - (c - 1) * (m_x - m0)) < 1e-15
+
+
+def test_step_a_constant_flow_is_not_a_decrease():
+    """A flat lambda_bar = b (no eigenvalue moves) never decreases: equal steps c*b
+    up to m_max, ceil((m_max - m_0)/(c b)) of them."""
+    b, m0, c, m_max = 0.25, 0.0, 1.9, 3.0
+    out, trace = sign.step_a(lambda m: b, m0, c, m_max)
+    assert out == "W=1"
+    n_expect = int(np.floor((m_max - m0) / (c * b))) + 1
+    assert len(trace) == n_expect + 1
+    assert all(abs(t[0] - (m0 + i * c * b)) < 1e-12 for i, t in enumerate(trace))
+
+
+def test_step_a_two_flows_switching_minimum():
+    """lambda_bar = min(m - a, d - 0.2 m): the first flow rises faster, the second
+    falls; step A follows the first until the minimum switches to the falling
+    one, and stops with B at the first evaluation where it is smaller."""
+    a, d, m0, c = -0.1, 0.9, 0.0, 1.9
 
     def lb(m):
-        return np.min(np.abs(a + s * m))
+        return min(m - a, d - 0.2 * m)
 
-    out, trace = sign.step_a(lb, 0.1, 1.9, 5.0)
-    ms = [t[0] for t in trace]
-    # every step respects the exclusion interval
-    for (m, l), m2 in zip(trace[:-1], ms[1:]):
-        assert m2 - m <= 1.9 * l + 1e-15
-    assert out in ("B", "W=1")
+    out, trace = sign.step_a(lb, m0, c, 50.0)
+    ms = [m0]
+    while True:
+        m = ms[-1] + c * lb(ms[-1])
+        ms.append(m)
+        if lb(m) < lb(ms[-2]):
+            break
+    assert out == "B"
+    assert [t[0] for t in trace] == pytest.approx(ms, abs=1e-14)
+    # every step stays inside the exclusion interval of its start
+    for (m, l), (m2, _) in zip(trace[:-1], trace[1:]):
+        assert m2 - m <= c * l + 1e-15
