@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 
 #include "../../include/cstar.h"
@@ -92,6 +93,14 @@ struct ApplyArgs {
     double shift = 0.0;
 };
 hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s);
+// Schedule of a multi-RHS time-marching launch (tune.cpp): the fastest of the
+// kMarchSchedules candidates for this (precision, lattice, nrhs, epilogue),
+// measured with HIP events on the first such launch, or read from the cache
+// file named by CSTAR_TUNE_CACHE; CSTAR_MARCH_SCHEDULE forces one.  launch(s)
+// issues the whole apply with schedule s (every schedule gives the same result).
+constexpr int kMarchSchedules = 5;
+int march_schedule(const Geo &g, cstar_prec prec, const ApplyArgs &a, hipStream_t s,
+                   const std::function<void(int)> &launch);
 // launch_apply on the handle's stream, with event timing when enabled (timing.cpp)
 hipError_t handle_apply(cstar_gauge *g, cstar_prec prec, const ApplyArgs &a);
 void timing_release(cstar_gauge *g);

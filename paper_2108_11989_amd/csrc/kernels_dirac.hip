@@ -15,6 +15,9 @@
 //              - 1/2 sum_mu [(1-g_mu) V(x,mu) psi(x+mu) + (1+g_mu) V(x-mu,mu)^H psi(x-mu)].
 // C* on the doubled lattice: the copy of x at x1+L sees conj(U), -theta; a hop
 // that leaves [0,L) in x1, x2 or x3 lands on the other copy.
+#include <functional>
+#include <type_traits>
+
 #include "lattice_dev.h"
 
 namespace cstar {
@@ -740,6 +743,291 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march(
     }
 }
 
+// Multi-RHS form of the time-marching kernel: every lane applies NR
+// right-hand sides to its site, so each link and clover word it loads serves
+// NR spinors (the loads of the gauge field per right-hand side, and their
+// bytes, fall by NR).  The sweep is that of k_apply_march; the exchange
+// buffer holds the NR payloads of every lane.  Launch item = (tile, group of
+// NR right-hand sides), groups fastest, so the groups of one tile run
+// together on one XCD and share the remaining gauge reads in its L2.
+template <class Fmt, int MU, int LOG2L, int NR>
+__device__ __forceinline__ void hop_fwd_mem_nr(const Geo &g, const typename Prec<Fmt>::V *__restrict__ in, long stride,
+                                               int p, int c, int t, int x1, int x2, int x3,
+                                               const Link<typename Prec<Fmt>::R> &Lk,
+                                               cx<typename Prec<Fmt>::R> acc[NR][12]) {
+    using R = typename Prec<Fmt>::R;
+    const Hop n = hop_fwd<MU, LOG2L>(g, t, x1, x2, x3);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cx<R> v[12], hh[6], gg[6];
+        SpinorIO<R>::load(in + r * stride, g, 1 - p, n.h, c ^ n.flip, v);
+        project<MU, -1>(v, hh);
+        link_mul<Fmt, false>(Lk, hh, gg);
+        accumulate<MU, -1>(acc[r], gg);
+    }
+}
+template <class Fmt, int MU, int LOG2L, int NR>
+__device__ __forceinline__ void hop_bwd_mem_nr(const Geo &g, const GaugeDev &d, const typename Prec<Fmt>::V *__restrict__ in,
+                                               long stride, int p, int c, int t, int x1, int x2, int x3,
+                                               cx<typename Prec<Fmt>::R> acc[NR][12]) {
+    using R = typename Prec<Fmt>::R;
+    const Hop n = hop_bwd<MU, LOG2L>(g, t, x1, x2, x3);
+    const int cn = c ^ n.flip;
+    Link<R> Lk;
+    Fmt::load(d, g, 1 - p, MU, n.h, cn ? R(-1) : R(1), Lk);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cx<R> v[12], hh[6], gg[6];
+        SpinorIO<R>::load(in + r * stride, g, 1 - p, n.h, cn, v);
+        project<MU, 1>(v, hh);
+        link_mul<Fmt, true>(Lk, hh, gg);
+        accumulate<MU, 1>(acc[r], gg);
+    }
+}
+
+template <class R, int NR>
+__device__ __forceinline__ void pin_nr(cx<R> acc[NR][12]) {
+#pragma unroll
+    for (int r = 0; r < NR; r++) pin(acc[r]);
+}
+
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool EPI>
+__global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march_nr(
+    Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
+    long stride, int ngrp, int gamma5, const double *__restrict__ masses, double mass0,
+    Epi<typename Prec<Fmt>::V> ep) {
+    using R = typename Prec<Fmt>::R;
+    using V = typename Prec<Fmt>::V;
+    constexpr int L = 1 << LOG2L;
+    constexpr int N1 = L / RX1, N2 = L / RX2;
+    constexpr int LANES = RX1 * RX2 * (2 << LOG2L);
+    const int nseg = (g.T + TB - 1) / TB;
+    const int per_grp = N1 * N2 * nseg;
+    const int item = xcd_tile(gridDim.x);
+    const int grp = item % ngrp;
+    int r_ = item / ngrp;
+    if (r_ >= per_grp) return;
+    const int tile2 = r_ % N2;
+    r_ /= N2;
+    const int tile1 = r_ % N1;
+    const int seg = r_ / N1;
+    const int lane = threadIdx.x;
+    const int c = lane & 1;
+    const int x3 = (lane >> 1) & (L - 1);
+    const int row = lane >> (LOG2L + 1);
+    const int x2_in = row % RX2, x1_in = row / RX2;
+    const int x2 = tile2 * RX2 + x2_in;
+    const int x1 = tile1 * RX1 + x1_in;
+    const int t0 = seg * TB;
+    const int t1 = min(t0 + TB, g.T);
+    const int j0 = grp * NR;
+    R dmu[NR], dml[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const double mass = masses ? masses[j0 + r] : mass0;
+        dmu[r] = R(4.0 + mass + ep.shift);
+        dml[r] = R(4.0 + mass - ep.shift);
+    }
+    __shared__ cx<R> xch[NR][3][6][LANES];
+    const V *inj = in + j0 * stride;
+    V *outj = out + j0 * stride;
+    const int xs = x1 + x2 + x3;
+    const R tsign = g.time_bc < 0 ? R(-1) : R(1);
+    const R csg = c ? R(-1) : R(1);
+
+    cx<R> hb[NR][6];
+    {
+        const int tp = t0 == 0 ? g.T - 1 : t0 - 1;
+        const int pp = (tp + xs) & 1, hp = pair_index<LOG2L>(g, tp, x1, x2, x3);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> v[12];
+            SpinorIO<R>::load(inj + r * stride, g, pp, hp, c, v);
+            project<0, 1>(v, hb[r]);
+            if (t0 == 0) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) hb[r][k] = scale(hb[r][k], tsign);
+            }
+        }
+    }
+    cx<R> acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[r][k] = {R(0), R(0)};
+#pragma nounroll
+    for (int s = t0; s <= t1; s++) {
+        const int ts = s == g.T ? 0 : s;
+        const int tm = s == 0 ? g.T - 1 : s - 1;
+        const int ps = (ts + xs) & 1, pm = (tm + xs) & 1;
+        const int hs = pair_index<LOG2L>(g, ts, x1, x2, x3), hm = pair_index<LOG2L>(g, tm, x1, x2, x3);
+        cx<R> v[NR][12];
+#pragma unroll
+        for (int r = 0; r < NR; r++) SpinorIO<R>::load(inj + r * stride, g, ps, hs, c, v[r]);
+        Link<R> Lt;  // V(s-1, 0) at the lane's spatial site
+        Fmt::load(d, g, pm, 0, hm, csg, Lt);
+        if (s > t0) {
+            // forward time hop of site s-1, then site s-1 is complete
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                cx<R> hf[6], gf[6];
+                project<0, -1>(v[r], hf);
+                if (s == g.T) {
+#pragma unroll
+                    for (int k = 0; k < 6; k++) hf[k] = scale(hf[k], tsign);
+                }
+                link_mul<Fmt, false>(Lt, hf, gf);
+                accumulate<0, -1>(acc[r], gf);
+                if constexpr (EPI) {
+                    finish_site<R, V>(g, outj + r * stride, ep, j0 + r, (long)(j0 + r) * stride, pm, hm, c, gamma5,
+                                      acc[r]);
+                } else {
+                    const R s5 = gamma5 ? R(-1) : R(1);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) acc[r][k] = scale(acc[r][k], k < 6 ? R(-0.5) : R(-0.5) * s5);
+                    SpinorIO<R>::store(outj + r * stride, g, pm, hm, c, acc[r]);
+                }
+            }
+        }
+        if (s < t1) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[r][k] = {R(0), R(0)};
+                cx<R> gb[6];
+                link_mul<Fmt, true>(Lt, hb[r], gb);
+                accumulate<0, 1>(acc[r], gb);
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[r][k] = scale(acc[r][k], R(-0.5));
+            }
+            pin_nr<R, NR>(acc);
+            // clover: each chirality block loaded once, applied to every right-hand side
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                R dg[6];
+                cx<R> o[15];
+                CloverIO<R>::template load<false>(d, g, ps, hs, b, dg, o);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    cx<R> u[6], w[6];
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        const cx<R> c0 = v[r][6 * b + a], c1 = v[r][6 * b + 3 + a];
+                        u[a] = c ? mk(-c1.im, -c1.re) : c0;
+                        u[3 + a] = c ? mk(c0.im, c0.re) : c1;
+                    }
+                    herm6_mul(dg, o, u, w);
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        const cx<R> q0 = c ? mk(w[3 + a].im, w[3 + a].re) : w[a];
+                        const cx<R> q1 = c ? mk(-w[a].im, -w[a].re) : w[3 + a];
+                        acc[r][6 * b + a] = acc[r][6 * b + a] + q0;
+                        acc[r][6 * b + 3 + a] = acc[r][6 * b + 3 + a] + q1;
+                    }
+                }
+                pin_nr<R, NR>(acc);
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+#pragma unroll
+                for (int k = 0; k < 12; k++)
+                    acc[r][k] = scale(acc[r][k] + scale(v[r][k], k < 6 ? dmu[r] : dml[r]), R(-2));
+                project<0, 1>(v[r], hb[r]);
+            }
+            pin_nr<R, NR>(acc);
+            int cj_ = c, x1j = x1, x2j = x2, x3j = x3;
+            asm volatile("" : "+v"(cj_), "+v"(x1j), "+v"(x2j), "+v"(x3j));
+            {
+                // x3 hops through the wave, one link for every right-hand side
+                static_assert(LOG2L <= 5, "an x3 row must fit in one wave");
+                const int wl = threadIdx.x & 63;
+                const int rowbase = wl & ~(2 * L - 1);
+                const int src_f = x3j < L - 1 ? wl + 2 : rowbase + (1 - cj_);
+                const int src_b = x3j > 0 ? wl - 2 : rowbase + 2 * (L - 1) + (1 - cj_);
+                Link<R> L3;
+                Fmt::load(d, g, ps, 3, hs, csg, L3);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    cx<R> hh[6], gg[6];
+                    project<3, 1>(v[r], hh);
+                    link_mul<Fmt, true>(L3, hh, gg);
+#pragma unroll
+                    for (int i = 0; i < 6; i++) hh[i] = {lane_get(src_b, gg[i].re), lane_get(src_b, gg[i].im)};
+                    accumulate<3, 1>(acc[r], hh);
+                    project<3, -1>(v[r], gg);
+#pragma unroll
+                    for (int i = 0; i < 6; i++) hh[i] = {lane_get(src_f, gg[i].re), lane_get(src_f, gg[i].im)};
+                    link_mul<Fmt, false>(L3, hh, gg);
+                    accumulate<3, -1>(acc[r], gg);
+                }
+            }
+            pin_nr<R, NR>(acc);
+            Link<R> L2;
+            Fmt::load(d, g, ps, 2, hs, csg, L2);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                cx<R> hh[6], gg[6];
+                project<2, -1>(v[r], hh);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[r][0][i][lane] = hh[i];
+                project<2, 1>(v[r], hh);
+                link_mul<Fmt, true>(L2, hh, gg);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[r][1][i][lane] = gg[i];
+                project<1, -1>(v[r], hh);
+#pragma unroll
+                for (int i = 0; i < 6; i++) xch[r][2][i][lane] = hh[i];
+            }
+            __syncthreads();
+            if (x2_in + 1 < RX2) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    cx<R> hh[6], gg[6];
+#pragma unroll
+                    for (int i = 0; i < 6; i++) hh[i] = xch[r][0][i][lane + 2 * L];
+                    link_mul<Fmt, false>(L2, hh, gg);
+                    accumulate<2, -1>(acc[r], gg);
+                }
+            } else {
+                hop_fwd_mem_nr<Fmt, 2, LOG2L, NR>(g, inj, stride, ps, cj_, ts, x1j, x2j, x3j, L2, acc);
+            }
+            pin_nr<R, NR>(acc);
+            if (x2_in > 0) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    cx<R> gg[6];
+#pragma unroll
+                    for (int i = 0; i < 6; i++) gg[i] = xch[r][1][i][lane - 2 * L];
+                    accumulate<2, 1>(acc[r], gg);
+                }
+            } else {
+                hop_bwd_mem_nr<Fmt, 2, LOG2L, NR>(g, d, inj, stride, ps, cj_, ts, x1j, x2j, x3j, acc);
+            }
+            pin_nr<R, NR>(acc);
+            {
+                Link<R> L1;
+                Fmt::load(d, g, ps, 1, hs, csg, L1);
+                if (x1_in + 1 < RX1) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        cx<R> hh[6], gg[6];
+#pragma unroll
+                        for (int i = 0; i < 6; i++) hh[i] = xch[r][2][i][lane + RX2 * 2 * L];
+                        link_mul<Fmt, false>(L1, hh, gg);
+                        accumulate<1, -1>(acc[r], gg);
+                    }
+                } else {
+                    hop_fwd_mem_nr<Fmt, 1, LOG2L, NR>(g, inj, stride, ps, cj_, ts, x1j, x2j, x3j, L1, acc);
+                }
+            }
+            pin_nr<R, NR>(acc);
+            __syncthreads();  // the exchange buffer is rewritten in the next slice
+            hop_bwd_mem_nr<Fmt, 1, LOG2L, NR>(g, d, inj, stride, ps, cj_, ts, x1j, x2j, x3j, acc);
+            pin_nr<R, NR>(acc);
+        }
+    }
+}
+
 // rows of a marching workgroup: 1024 lanes for the FP32 forms, 512 for FP64
 template <class Fmt>
 struct March {
@@ -752,34 +1040,111 @@ struct March<FmtF64> {
 constexpr int march_rows(int lanes, int log2l) { return lanes >> (log2l + 1); }
 constexpr int march_rx1(int rows) { return rows >= 64 ? 8 : rows >= 16 ? 4 : 2; }
 
+// Multi-RHS launch of the time-marching form over right-hand sides
+// [j_begin, j_begin + NR * ngrp): pointers, masses and epilogue operands are
+// shifted to the first of them.
+template <class V>
+static Epi<V> shift_epi(const Epi<V> &ep, long off, int j_begin, bool fp64) {
+    Epi<V> e = ep;
+    if (e.y) e.y += off;
+    if (e.z) e.z += off;
+    if (e.w) e.w += off;
+    if (e.ew) e.ew = fp64 ? (const void *)((const double *)e.ew + j_begin) : (const void *)((const float *)e.ew + j_begin);
+    return e;
+}
+
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR>
+static void launch_march_nr(const Geo &g, const GaugeDev &d, const ApplyArgs &a, const Epi<typename Prec<Fmt>::V> &ep,
+                            int j_begin, int ngrp, hipStream_t s) {
+    using V = typename Prec<Fmt>::V;
+    constexpr int LANES = RX1 * RX2 * (2 << LOG2L);
+    const long st = a.stride / (long)sizeof(V);
+    const long off = (long)j_begin * st;
+    const Epi<V> e = shift_epi(ep, off, j_begin, sizeof(typename Prec<Fmt>::R) == 8);
+    const int nseg = (g.T + TB - 1) / TB;
+    const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * ngrp;
+    const int nwg = (int)((items + 7) / 8 * 8);
+    const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
+    if (e.on)
+        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, true>), dim3(nwg), dim3(LANES), 0, s, g, d,
+                           (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e);
+    else
+        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, false>), dim3(nwg), dim3(LANES), 0, s, g,
+                           d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e);
+}
+
+// Single-RHS-per-lane time-marching launch over right-hand sides [j_begin, j_begin + n).
 template <class Fmt, int LOG2L>
-static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
+static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, const Epi<typename Prec<Fmt>::V> &ep,
+                           int j_begin, int n, hipStream_t s) {
+    using V = typename Prec<Fmt>::V;
+    constexpr int rows = march_rows(March<Fmt>::lanes, LOG2L);
+    constexpr int RX1 = march_rx1(rows), RX2 = rows / RX1;
+    constexpr int TB = 8;
+    static_assert(RX1 * RX2 * (2 << LOG2L) == March<Fmt>::lanes, "march tile");
+    const long st = a.stride / (long)sizeof(V);
+    const long off = (long)j_begin * st;
+    const Epi<V> e = shift_epi(ep, off, j_begin, sizeof(typename Prec<Fmt>::R) == 8);
+    const int nseg = (g.T + TB - 1) / TB;
+    const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * n;
+    const int nwg = (int)((items + 7) / 8 * 8);
+    const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
+    // epilogue compiled in only where used; clover streamed only when one right-hand side reads it
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d, (const V *)a.in + off,
+                           (V *)a.out + off, st, n, a.gamma5, m, a.mass0, e);
+    };
+    const bool one = n == 1;
+    if (e.on) {
+        if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, true>);
+        else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, false>);
+    } else {
+        if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, true>);
+        else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, false>);
+    }
+}
+
+// Schedules of a multi-RHS launch of the FP32 forms at L = 32 (the tuner's candidates):
+//   0: one right-hand side per lane, 1024-lane workgroups of 4 x 4 rows, 8 slices;
+//   1: two per lane, 512 lanes, 2 x 4 rows, 8 slices;   2: two per lane, 4 x 2 rows, 8 slices;
+//   3: two per lane, 2 x 4 rows, 16 slices;             4: four per lane, 256 lanes, 2 x 2 rows, 8 slices.
+// Right-hand sides beyond the last full group of a schedule go to schedule 0.
+constexpr int march_nr_of(int sched) { return sched == 0 ? 1 : sched == 4 ? 4 : 2; }
+
+template <class Fmt>
+static void launch_march_sched32(int sched, const Geo &g, const GaugeDev &d, const ApplyArgs &a,
+                                 const Epi<typename Prec<Fmt>::V> &ep, hipStream_t s) {
+    const int nr = march_nr_of(sched);
+    const int ngrp = a.nrhs / nr;
+    const int done = ngrp * nr;
+    if (ngrp > 0) {
+        switch (sched) {
+            case 1: launch_march_nr<Fmt, 5, 2, 4, 8, 2>(g, d, a, ep, 0, ngrp, s); break;
+            case 2: launch_march_nr<Fmt, 5, 4, 2, 8, 2>(g, d, a, ep, 0, ngrp, s); break;
+            case 3: launch_march_nr<Fmt, 5, 2, 4, 16, 2>(g, d, a, ep, 0, ngrp, s); break;
+            case 4: launch_march_nr<Fmt, 5, 2, 2, 8, 4>(g, d, a, ep, 0, ngrp, s); break;
+            default: launch_march_1<Fmt, 5>(g, d, a, ep, 0, a.nrhs, s); return;
+        }
+    }
+    if (done < a.nrhs) launch_march_1<Fmt, 5>(g, d, a, ep, done, a.nrhs - done, s);
+}
+
+template <class Fmt, int LOG2L>
+static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s, cstar_prec prec) {
     using V = typename Prec<Fmt>::V;
     Epi<V> ep{(const V *)a.y, (const V *)a.z, (float)a.ea, (float)a.eb, (float)a.ec, a.ea, a.eb, a.ec,
               (a.y || a.z || a.w || a.ea != 1.0) ? 1 : 0, (const V *)a.w, a.ew, a.shift};
     const long st = a.stride / (long)sizeof(V);
     const int ntiles = (4 * g.Vh + 255) / 256;
-    if constexpr (LOG2L >= 3) {
-        constexpr int rows = march_rows(March<Fmt>::lanes, LOG2L);
-        constexpr int RX1 = march_rx1(rows), RX2 = rows / RX1;
-        constexpr int TB = 8;
-        static_assert(RX1 * RX2 * (2 << LOG2L) == March<Fmt>::lanes, "march tile");
-        const int nseg = (g.T + TB - 1) / TB;
-        const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * a.nrhs;
-        const int nwg = (int)((items + 7) / 8 * 8);
-        // epilogue compiled in only where used; clover streamed only when one right-hand side reads it
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d, (const V *)a.in, (V *)a.out, st,
-                               a.nrhs, a.gamma5, a.masses_dev, a.mass0, ep);
-        };
-        const bool one = a.nrhs == 1;
-        if (ep.on) {
-            if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, true>);
-            else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, false>);
-        } else {
-            if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, true>);
-            else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, false, false>);
+    if constexpr (LOG2L == 5 && !std::is_same<Fmt, FmtF64>::value) {
+        if (a.nrhs > 1) {
+            auto go = [&](int sched) { launch_march_sched32<Fmt>(sched, g, d, a, ep, s); };
+            go(march_schedule(g, prec, a, s, go));
+            return;
         }
+    }
+    if constexpr (LOG2L >= 3) {
+        launch_march_1<Fmt, LOG2L>(g, d, a, ep, 0, a.nrhs, s);
         return;
     }
     if constexpr (LOG2L >= 2) {
@@ -806,24 +1171,24 @@ static void launch_apply_l(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
 }
 
 template <class Fmt>
-static void launch_apply_t(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s) {
+static void launch_apply_t(const Geo &g, const GaugeDev &d, const ApplyArgs &a, hipStream_t s, cstar_prec prec) {
     switch (g.L) {
-        case 4: launch_apply_l<Fmt, 2>(g, d, a, s); break;
-        case 8: launch_apply_l<Fmt, 3>(g, d, a, s); break;
-        case 16: launch_apply_l<Fmt, 4>(g, d, a, s); break;
-        case 32: launch_apply_l<Fmt, 5>(g, d, a, s); break;
-        case 64: launch_apply_l<Fmt, 6>(g, d, a, s); break;
-        default: launch_apply_l<Fmt, 0>(g, d, a, s); break;
+        case 4: launch_apply_l<Fmt, 2>(g, d, a, s, prec); break;
+        case 8: launch_apply_l<Fmt, 3>(g, d, a, s, prec); break;
+        case 16: launch_apply_l<Fmt, 4>(g, d, a, s, prec); break;
+        case 32: launch_apply_l<Fmt, 5>(g, d, a, s, prec); break;
+        case 64: launch_apply_l<Fmt, 6>(g, d, a, s, prec); break;
+        default: launch_apply_l<Fmt, 0>(g, d, a, s, prec); break;
     }
 }
 
 hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s) {
     if (prec == CSTAR_FP64)
-        launch_apply_t<FmtF64>(g, d, a, s);
+        launch_apply_t<FmtF64>(g, d, a, s, prec);
     else if (prec == CSTAR_FP32)
-        launch_apply_t<FmtF32>(g, d, a, s);
+        launch_apply_t<FmtF32>(g, d, a, s, prec);
     else
-        launch_apply_t<FmtBF16>(g, d, a, s);
+        launch_apply_t<FmtBF16>(g, d, a, s, prec);
     return hipGetLastError();
 }
 

@@ -1,0 +1,108 @@
+"""Multi-RHS schedules of the apply at L = 32 (where the time-marching kernel
+can apply several right-hand sides per lane), through the C ABI.
+
+Every schedule of the tuner (CSTAR_MARCH_SCHEDULE forces one) must give, for
+every right-hand side of a multi-RHS launch, the bits of a single-RHS launch
+of that input at that mass -- the schedules differ only in how sites and
+right-hand sides are dealt to lanes, not in the arithmetic of a site -- and
+one right-hand side is checked against the oracle in its BF16-link emulation
+mode (max |diff| <= 2e-6 max |ref|, FP32 arithmetic over ~100 terms).
+Widths cover a full group, a group plus a remainder and the bench's 16.
+
+The fused epilogue of these kernels runs inside the eigensolver's filter: the
+mixed-precision solve on a 4x32^3 lattice must reproduce the FP64 solve's
+eigenvalues within their residual bounds.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dirac as odirac
+from paper_2108_11989_amd import cstar, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+T, L = 4, 32
+SCHEDULES = range(5)
+
+
+@pytest.fixture(scope="module")
+def field():
+    su3, th = synth.make_field(T, L, 0.3, 31)
+    return su3, th
+
+
+def _apply(g, canon, masses, prec, gamma5):
+    n = canon.shape[0]
+    nin, nout = g.new_native(n, prec), g.new_native(n, prec)
+    g.pack(canon, nin, prec, n)
+    g.apply(nin, nout, masses, prec, gamma5)
+    res = torch.empty_like(canon)
+    g.unpack(nout, res, prec, n)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("prec", [cstar.FP32_BF16LINKS, cstar.FP32])
+def test_schedules_bitwise_equal_to_single_rhs(field, prec):
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    su3, th = field
+    g = cstar.Gauge(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1)
+    nmax = 16
+    masses = list(np.linspace(-0.4, 1.3, nmax))
+    psi = synth.random_spinor(T, L, 77, nrhs=nmax, dtype=np.complex64)
+    canon = torch.from_numpy(psi).cuda().contiguous()
+    singles = [_apply(g, canon[j:j + 1].contiguous(), masses[j:j + 1], prec, True)[0] for j in range(nmax)]
+    try:
+        for sched in SCHEDULES:
+            os.environ["CSTAR_MARCH_SCHEDULE"] = str(sched)
+            for n in (2, 3, 5, 16):
+                print(f"schedule {sched} nrhs {n} prec {prec}", flush=True)
+                multi = _apply(g, canon[:n].contiguous(), masses[:n], prec, True)
+                for j in range(n):
+                    assert torch.equal(multi[j], singles[j]), (sched, n, j)
+    finally:
+        os.environ.pop("CSTAR_MARCH_SCHEDULE", None)
+    mode = 2 if prec == cstar.FP32_BF16LINKS else 1
+    op = odirac.Operator(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, link_mode=mode)
+    j = 5
+    ref = op.apply(psi[j].astype(np.complex128), masses[j], True)
+    out = singles[j].cpu().numpy().astype(np.complex128)
+    assert np.abs(out - ref).max() <= 2e-6 * np.abs(ref).max()
+    g.close()
+
+
+def test_tuned_launch_equals_single_rhs(field):
+    """Without a forced schedule the tuner picks one on the first launch of a
+    kind; the result is still the single-RHS one."""
+    su3, th = field
+    os.environ.pop("CSTAR_MARCH_SCHEDULE", None)
+    g = cstar.Gauge(su3, th, -1 / 3, synth.CSW_SU3, synth.CSW_U1, time_bc=-1)
+    prec = cstar.FP32_BF16LINKS
+    masses = [-0.2, 0.0, 0.3, 0.8, 1.5, 2.0, 3.0]
+    psi = synth.random_spinor(T, L, 78, nrhs=len(masses), dtype=np.complex64)
+    canon = torch.from_numpy(psi).cuda().contiguous()
+    for _ in range(2):  # the first call tunes, the second uses the choice
+        multi = _apply(g, canon, masses, prec, False)
+        for j in range(len(masses)):
+            single = _apply(g, canon[j:j + 1].contiguous(), masses[j:j + 1], prec, False)[0]
+            assert torch.equal(multi[j], single)
+    g.close()
+
+
+def test_mixed_eigensolve_at_l32_matches_fp64(field):
+    su3, th = field
+    g = cstar.Gauge(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1)
+    m0 = float(synth.kappa_to_m0(0.128))
+    k = 4
+    print("fp64 solve", flush=True)
+    e64, r64, _ = g.lowest_eigs(m0, k, cstar.eig_opts(inner=cstar.FP64, tol=1e-11, max_iter=400))
+    print("mixed solve", flush=True)
+    emx, rmx, st = g.lowest_eigs(m0, k, cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=1e-11, max_iter=400))
+    print(e64, emx, st.applies_inner, st.applies_fp64, flush=True)
+    assert st.applies_inner > 0
+    assert np.all(np.abs(e64 - emx) <= r64 + rmx + 1e-14)
+    assert np.all(np.abs(e64 - emx) <= 1e-10 * np.abs(e64))
+    g.close()
