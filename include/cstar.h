@@ -114,6 +114,21 @@ cstar_status cstar_spinor_unpack(cstar_gauge *g, cstar_prec prec, int nrhs, cons
 cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
                          const void *in, void *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments, layouts and results as dirac_apply, with no device
+ * allocation and no schedule measurement (a schedule already chosen by the
+ * tuner, else a fixed default).  The per-RHS masses are staged in a
+ * library-owned device array of CSTAR_NOALLOC_MAX_RHS doubles (8 KiB per GPU,
+ * held until the process ends), shared by every call on that GPU: calls that
+ * overlap on one GPU race on it.  Asynchronous on the handle's stream.
+ * Errors: EINVAL (as dirac_apply, and nrhs > CSTAR_NOALLOC_MAX_RHS), EDEVICE.
+ */
+#define CSTAR_NOALLOC_MAX_RHS 1024
+cstar_status dirac_apply_noalloc(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
+                                 const void *in, void *out);
+
 typedef struct {
     cstar_prec inner;        /* precision of the filter applies (FP64 or an FP32 form) */
     double tol;              /* target: residual ||Q v - lambda v|| <= tol * max(|lambda|, lambda_floor) */

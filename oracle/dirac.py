@@ -44,6 +44,7 @@ def lib():
         L.oracle_links.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_int, dp]
         L.oracle_dirac_tab.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double,
                                        ctypes.c_int, dp, dp]
+        L.oracle_local_term.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
         L.oracle_gammas.argtypes = [dp]
         L.oracle_neighbours.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long)]
         L.oracle_transport.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
@@ -125,6 +126,14 @@ class Operator:
                                     int(direction), self.link_mode, _p(psi), _p(out))
         if rc != 0:
             raise MemoryError("oracle_transport failed")
+        return out
+
+    def local_term(self, m0: float) -> np.ndarray:
+        """Site-local 12x12 part of D(m0) on every doubled site, complex [2V][12][12]
+        (index 3*spin + colour): (4+m0) 1 + SW(x)."""
+        out = np.empty((self.nsites, 12, 12), dtype=np.complex128)
+        F = _p(self.F) if self.F is not None else None
+        lib().oracle_local_term(self.T, self.L, F, float(m0), _p(out))
         return out
 
     def D(self, psi, m0):

@@ -408,6 +408,47 @@ int oracle_dirac(int T, int L, int time_bc, double q, const double *su3, const d
     return rc;
 }
 
+/*
+ * Site-local part of D on every doubled site (it is what D keeps when it is
+ * restricted to one parity of sites, as in the even-odd decomposition of the
+ * mass-reweighting section):
+ *   out[s][a*3+i][b*3+j] = (4+m0) delta_ab delta_ij + (i/2) sum_{mu<nu} sigma_{mu nu}[a][b] F_{mu nu}(s)[i][j],
+ * complex double; F from oracle_field_strength (NULL: no clover term).
+ */
+int oracle_local_term(int T, int L, const double *F, double m0, double *out) {
+    init_gamma();
+    geom g = {T, L, 1};
+    long n = n_sites(&g);
+    static const int planes[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        cplx M[12][12];
+        for (int r = 0; r < 12; r++)
+            for (int c = 0; c < 12; c++) M[r][c] = (r == c) ? (4.0 + m0) : 0.0;
+        if (F) {
+            for (int p = 0; p < 6; p++) {
+                int mu = planes[p][0], nu = planes[p][1];
+                const double *f = F + ((s * 6 + p) * 9) * 2;
+                for (int a = 0; a < 4; a++)
+                    for (int b = 0; b < 4; b++) {
+                        cplx sab = 0.5 * I * SIGMA[mu][nu][a][b];
+                        if (sab == 0) continue;
+                        for (int i = 0; i < 3; i++)
+                            for (int j = 0; j < 3; j++)
+                                M[a * 3 + i][b * 3 + j] += sab * (f[(i * 3 + j) * 2] + I * f[(i * 3 + j) * 2 + 1]);
+                    }
+            }
+        }
+        double *o = out + s * 288;
+        for (int r = 0; r < 12; r++)
+            for (int c = 0; c < 12; c++) {
+                o[(r * 12 + c) * 2] = creal(M[r][c]);
+                o[(r * 12 + c) * 2 + 1] = cimag(M[r][c]);
+            }
+    }
+    return 0;
+}
+
 /* Gamma matrices as used above (for the oracle's own self-tests):
  * out[6][4][4] complex = g0,g1,g2,g3,g5,1. */
 void oracle_gammas(double *out) {

@@ -75,9 +75,10 @@ def lanczos_q2(op, m0: float, want: int, basis: int = 0, keep: int = 0, tol: flo
             w = A(V[j])
             matvecs += 1
             # two passes of classical Gram-Schmidt against the whole basis
-            h = V[: j + 1].conj() @ w
+            # (V^H w formed as conj(V conj(w)): no conjugated copy of the basis)
+            h = (V[: j + 1] @ w.conj()).conj()
             w -= V[: j + 1].T @ h
-            h2 = V[: j + 1].conj() @ w
+            h2 = (V[: j + 1] @ w.conj()).conj()
             w -= V[: j + 1].T @ h2
             h += h2
             H[: j + 1, j] = h

@@ -91,6 +91,9 @@ struct ApplyArgs {
     const void *ew = nullptr;
     // with gamma5: Q + shift = g5 (D + shift g5), a spin-dependent local mass
     double shift = 0.0;
+    // 1: never measure schedules (callers that must not synchronise or create
+    // events): a cached choice or the default schedule
+    int no_tune = 0;
 };
 hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const ApplyArgs &a, hipStream_t s);
 // Schedule of a multi-RHS time-marching launch (tune.cpp): the fastest of the

@@ -17,15 +17,18 @@ template <class R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <class R>
 __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+// Products are written with explicit FMAs (which product is fused is fixed),
+// so that every kernel rounds a site's arithmetic the same way whatever the
+// compiler would otherwise contract: launch schedules give identical bits.
 template <class R>
 __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 template <class R>
 __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
 template <class R>
 __device__ __forceinline__ cx<R> conjmul(cx<R> a, cx<R> b) {  // conj(a) * b
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re))};
 }
 template <class R>
 __device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
@@ -45,7 +48,7 @@ __device__ __forceinline__ cx<R> cmac_conj(cx<R> acc, cx<R> a, cx<R> b) {
 // a*b - c*d
 template <class R>
 __device__ __forceinline__ cx<R> cmul_sub(cx<R> a, cx<R> b, cx<R> c, cx<R> d) {
-    const cx<R> t = {c.re * d.re - c.im * d.im, c.re * d.im + c.im * d.re};
+    const cx<R> t = c * d;
     return cmac(cx<R>{-t.re, -t.im}, a, b);
 }
 

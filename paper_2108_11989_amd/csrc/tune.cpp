@@ -9,7 +9,8 @@
 // process.  With CSTAR_TUNE_CACHE=<file> the choices are read from and
 // appended to that file ("prec T L nrhs operands schedule" per line), so a
 // later process skips the measurement; CSTAR_MARCH_SCHEDULE=<n> forces
-// schedule n everywhere.
+// schedule n everywhere.  Launches that must not measure (ApplyArgs::no_tune)
+// take a choice already made, else schedule 1.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -64,6 +65,7 @@ int march_schedule(const Geo &g, cstar_prec prec, const ApplyArgs &a, hipStream_
     if (!g_loaded) load_cache();
     auto it = g_table.find(key);
     if (it != g_table.end()) return it->second;
+    if (a.no_tune) return 1;  // two right-hand sides per lane, 2 x 4 rows, 8 slices
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);

@@ -96,6 +96,7 @@ def lib():
         L.cstar_spinor_pack.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.cstar_spinor_unpack.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.dirac_apply.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.dirac_apply_noalloc.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.q_lowest_eigs.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(EigOpts), dp, dp, vp,
                                     ctypes.POINTER(EigStats)]
         L.q_lambda_bar_power.argtypes = [vp, ctypes.c_double, ctypes.POINTER(LbarOpts), dp, dp,
@@ -121,6 +122,7 @@ def lib():
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
+                     "dirac_apply_noalloc",
                      "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
@@ -227,6 +229,14 @@ class Gauge:
         m = np.ascontiguousarray(np.atleast_1d(np.asarray(masses, dtype=np.float64)))
         _check(lib().dirac_apply(self.h, len(m), _dp(m), prec, int(bool(gamma5)),
                                  ctypes.c_void_p(native_in.data_ptr()), ctypes.c_void_p(native_out.data_ptr())))
+
+    def apply_noalloc(self, native_in, native_out, masses, prec=FP64, gamma5=False):
+        """dirac_apply_noalloc: as apply, with no device allocation (masses staged in the
+        library's static device array)."""
+        m = np.ascontiguousarray(np.atleast_1d(np.asarray(masses, dtype=np.float64)))
+        _check(lib().dirac_apply_noalloc(self.h, len(m), _dp(m), prec, int(bool(gamma5)),
+                                         ctypes.c_void_p(native_in.data_ptr()),
+                                         ctypes.c_void_p(native_out.data_ptr())))
 
     def lowest_eigs(self, m0, k, opts: EigOpts | None = None, evecs=None, raise_on_noconv=True):
         ev = np.zeros(k)
