@@ -129,6 +129,31 @@ cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_p
 cstar_status dirac_apply_noalloc(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
                                  const void *in, void *out);
 
+/*
+ * Even-odd decomposition (paper, mass-reweighting section, eq. detQ2 and the
+ * definition of W_eo).  Sites of the doubled lattice are even or odd by
+ * parity (t+x1+x2+x3) mod 2; every hop changes it.  D_oo, the restriction of
+ * D to the odd sites, is the site-local term (4+m) + SW(x), and
+ *   D_hat = D_ee - D_eo D_oo^{-1} D_oe  (on the even sites),  Q_hat = g5 D_hat,
+ *   det D = det D_oo det D_hat.
+ * Even vector: the parity-0 half of a native spinor (its first
+ * cstar_even_bytes() bytes), per right-hand side.
+ */
+size_t cstar_even_bytes(const cstar_gauge *g, cstar_prec prec);
+/* out_j = D_hat(m0) in_j (gamma5 != 0: Q_hat), j < nrhs; in/out: device, nrhs
+ * even vectors each, non-aliasing.  The first call at a mass computes the
+ * inverse blocks of (4+m0) + SW on the odd sites in FP64 (kept for the next
+ * calls at that mass); the handle allocates them and an odd-site scratch
+ * vector per right-hand side on first use.  Asynchronous on the handle's
+ * stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+cstar_status dirac_eo_apply(cstar_gauge *g, int nrhs, double m0, cstar_prec prec, int gamma5, const void *in,
+                            void *out);
+/* log W_eo(m, m') = (1/2) log|det[D_oo(m') D_oo(m)^{-1}]|, exact, in FP64: the
+ * sum over odd sites of the log-moduli of the 6x6 block determinants (the
+ * conjugate copy of a site contributes the same modulus).  Synchronous.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+cstar_status cstar_log_w_eo(cstar_gauge *g, double m, double m_prime, double *log_w_eo);
+
 typedef struct {
     cstar_prec inner;        /* precision of the filter applies (FP64 or an FP32 form) */
     double tol;              /* target: residual ||Q v - lambda v|| <= tol * max(|lambda|, lambda_floor) */

@@ -153,6 +153,7 @@ void cstar_gauge_destroy(cstar_gauge *g) {
     (void)hipStreamSynchronize(g->stream);
     timing_release(g);
     workspace_release(g);
+    eo_release(g);
     if (g->extra) {
         HandleExtra *ex = (HandleExtra *)g->extra;
         if (ex->masses.dev) (void)hipFree(ex->masses.dev);

@@ -52,6 +52,7 @@ struct cstar_gauge {
     void *nn = nullptr;     // learned preconditioner state (nn.cpp), nullptr = none
     void *extra = nullptr;  // per-handle staging buffers (api.cpp)
     void *timing = nullptr; // apply-kernel event timing (timing.cpp), nullptr = off
+    void *eo = nullptr;     // even-odd state (eo.cpp): inverse blocks of the last mass, scratch
 };
 
 namespace cstar {
@@ -101,7 +102,7 @@ hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const 
 // measured with HIP events on the first such launch, or read from the cache
 // file named by CSTAR_TUNE_CACHE; CSTAR_MARCH_SCHEDULE forces one.  launch(s)
 // issues the whole apply with schedule s (every schedule gives the same result).
-constexpr int kMarchSchedules = 5;
+constexpr int kMarchSchedules = 7;
 int march_schedule(const Geo &g, cstar_prec prec, const ApplyArgs &a, hipStream_t s,
                    const std::function<void(int)> &launch);
 // launch_apply on the handle's stream, with event timing when enabled (timing.cpp)
@@ -110,6 +111,27 @@ void timing_release(cstar_gauge *g);
 
 hipError_t launch_pack_spinor(const Geo &g, cstar_prec prec, int nrhs, void *canon, void *native, int unpack,
                               hipStream_t s);
+
+// ---- even-odd decomposition (kernels_eo.hip) ------------------------------
+// D_hat psi_e on nrhs right-hand sides: in / out are parity-0 blocks (the first
+// half of a native vector, stride_in / stride_out bytes apart), tmp full native
+// vectors whose parity-1 blocks receive D_oo^{-1} D_oe psi_e; inv the inverse
+// blocks of (4+m) + SW on the odd sites (FP64 double2 [36][Vh], FP32 float4 [18][Vh]).
+struct EoArgs {
+    const void *in;
+    void *tmp;
+    void *out;
+    long stride_in, stride_tmp, stride_out;  // bytes
+    int nrhs;
+    double m;
+    int gamma5;
+    const void *inv;
+};
+int eo_pairs_blocks(const Geo &g);
+hipError_t launch_local_inv(const Geo &g, const GaugeDev &d, double m, double2 *inv64, float4 *inv32, hipStream_t s);
+hipError_t launch_logdet_ratio(const Geo &g, const GaugeDev &d, double m, double mp, double *partial, hipStream_t s);
+hipError_t launch_eo_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const EoArgs &e, hipStream_t s);
+void eo_release(cstar_gauge *g);
 
 // ---- BLAS on native vectors (kernels_blas.hip) -----------------------------
 // A native FP64 vector is an array of n2 = 24*Vh*... double2 entries (complex numbers);

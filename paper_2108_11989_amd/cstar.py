@@ -97,6 +97,10 @@ def lib():
         L.cstar_spinor_unpack.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.dirac_apply.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
         L.dirac_apply_noalloc.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.cstar_even_bytes.argtypes = [vp, ctypes.c_int]
+        L.cstar_even_bytes.restype = ctypes.c_size_t
+        L.dirac_eo_apply.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.cstar_log_w_eo.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp]
         L.q_lowest_eigs.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(EigOpts), dp, dp, vp,
                                     ctypes.POINTER(EigStats)]
         L.q_lambda_bar_power.argtypes = [vp, ctypes.c_double, ctypes.POINTER(LbarOpts), dp, dp,
@@ -122,7 +126,7 @@ def lib():
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
-                     "dirac_apply_noalloc",
+                     "dirac_apply_noalloc", "dirac_eo_apply", "cstar_log_w_eo",
                      "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
@@ -237,6 +241,16 @@ class Gauge:
         _check(lib().dirac_apply_noalloc(self.h, len(m), _dp(m), prec, int(bool(gamma5)),
                                          ctypes.c_void_p(native_in.data_ptr()),
                                          ctypes.c_void_p(native_out.data_ptr())))
+
+    def eo_apply(self, even_in, even_out, m0, prec=FP64, gamma5=False, nrhs=1):
+        """D_hat(m0) (gamma5: Q_hat) on nrhs even vectors (the parity-0 halves of native spinors)."""
+        _check(lib().dirac_eo_apply(self.h, int(nrhs), float(m0), prec, int(bool(gamma5)),
+                                    ctypes.c_void_p(even_in.data_ptr()), ctypes.c_void_p(even_out.data_ptr())))
+
+    def log_w_eo(self, m, m_prime) -> float:
+        v = ctypes.c_double()
+        _check(lib().cstar_log_w_eo(self.h, float(m), float(m_prime), ctypes.byref(v)))
+        return v.value
 
     def lowest_eigs(self, m0, k, opts: EigOpts | None = None, evecs=None, raise_on_noconv=True):
         ev = np.zeros(k)
