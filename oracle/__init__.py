@@ -11,6 +11,7 @@ Modules:
   pfaffian  -- Pfaffian of a complex antisymmetric matrix (pivoted reduction),
                brute-force expansion for tiny matrices
   sign      -- W_sgn from dense inertia and from the Pfaffian, step A of the paper
-  lanczos   -- Krylov eigenvalues of Q^2 for lattices too large for dense work
+  lanczos   -- eigenvalues of Q by Lanczos on Q^2, for lattices too large for dense work
+  evenodd   -- even-odd blocks of D, the Schur complement D_hat and the factor W_eo
   nn        -- forward/backward of the gauge-covariant preconditioner network
 """

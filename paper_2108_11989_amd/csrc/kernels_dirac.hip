@@ -15,6 +15,7 @@
 //              - 1/2 sum_mu [(1-g_mu) V(x,mu) psi(x+mu) + (1+g_mu) V(x-mu,mu)^H psi(x-mu)].
 // C* on the doubled lattice: the copy of x at x1+L sees conj(U), -theta; a hop
 // that leaves [0,L) in x1, x2 or x3 lands on the other copy.
+#include <algorithm>
 #include <functional>
 #include <type_traits>
 
@@ -579,10 +580,39 @@ __device__ __forceinline__ void pin_nr(cx<R> acc[NR][12]) {
 }
 
 template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool EPI>
+__device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
+                                              const typename Prec<Fmt>::V *__restrict__ in,
+                                              typename Prec<Fmt>::V *__restrict__ out, long stride, int ngrp,
+                                              int gamma5, const double *__restrict__ masses, double mass0,
+                                              const Epi<typename Prec<Fmt>::V> &ep, int item);
+
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool EPI, bool PERSIST>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march_nr(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
     long stride, int ngrp, int gamma5, const double *__restrict__ masses, double mass0,
-    Epi<typename Prec<Fmt>::V> ep) {
+    Epi<typename Prec<Fmt>::V> ep, int nitems) {
+    if constexpr (!PERSIST) {
+        march_nr_item<Fmt, LOG2L, RX1, RX2, TB, NR, EPI>(g, d, in, out, stride, ngrp, gamma5, masses, mass0, ep,
+                                                         xcd_tile(gridDim.x));
+    } else {
+        // persistent: workgroup w stays on XCD w mod 8 and walks that XCD's
+        // contiguous range of items (nitems is a multiple of 8) with the
+        // XCD's other workgroups; every thread of a workgroup takes the same
+        // items, so the slice barriers inside stay uniform
+        const int w = blockIdx.x, x = w & 7, nloc = gridDim.x >> 3;
+        const int per_xcd = nitems >> 3;
+        for (int k = w >> 3; k < per_xcd; k += nloc)
+            march_nr_item<Fmt, LOG2L, RX1, RX2, TB, NR, EPI>(g, d, in, out, stride, ngrp, gamma5, masses, mass0,
+                                                             ep, x * per_xcd + k);
+    }
+}
+
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool EPI>
+__device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
+                                              const typename Prec<Fmt>::V *__restrict__ in,
+                                              typename Prec<Fmt>::V *__restrict__ out, long stride, int ngrp,
+                                              int gamma5, const double *__restrict__ masses, double mass0,
+                                              const Epi<typename Prec<Fmt>::V> &ep, int item) {
     using R = typename Prec<Fmt>::R;
     using V = typename Prec<Fmt>::V;
     constexpr int L = 1 << LOG2L;
@@ -590,7 +620,6 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march_nr(
     constexpr int LANES = RX1 * RX2 * (2 << LOG2L);
     const int nseg = (g.T + TB - 1) / TB;
     const int per_grp = N1 * N2 * nseg;
-    const int item = xcd_tile(gridDim.x);
     const int grp = item % ngrp;
     int r_ = item / ngrp;
     if (r_ >= per_grp) return;
@@ -840,7 +869,7 @@ static Epi<V> shift_epi(const Epi<V> &ep, long off, int j_begin, bool fp64) {
     return e;
 }
 
-template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR>
+template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool PERSIST = false>
 static void launch_march_nr(const Geo &g, const GaugeDev &d, const ApplyArgs &a, const Epi<typename Prec<Fmt>::V> &ep,
                             int j_begin, int ngrp, hipStream_t s) {
     using V = typename Prec<Fmt>::V;
@@ -850,14 +879,16 @@ static void launch_march_nr(const Geo &g, const GaugeDev &d, const ApplyArgs &a,
     const Epi<V> e = shift_epi(ep, off, j_begin, sizeof(typename Prec<Fmt>::R) == 8);
     const int nseg = (g.T + TB - 1) / TB;
     const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * ngrp;
-    const int nwg = (int)((items + 7) / 8 * 8);
+    const int nitems = (int)((items + 7) / 8 * 8);
+    // persistent: two 256-lane workgroups per CU of the 256-CU chip
+    const int nwg = PERSIST ? std::min(nitems, 512) : nitems;
     const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
     if (e.on)
-        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, true>), dim3(nwg), dim3(LANES), 0, s, g, d,
-                           (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e);
+        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, true, PERSIST>), dim3(nwg), dim3(LANES), 0,
+                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems);
     else
-        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, false>), dim3(nwg), dim3(LANES), 0, s, g,
-                           d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e);
+        hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, false, PERSIST>), dim3(nwg), dim3(LANES), 0,
+                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems);
 }
 
 // Single-RHS-per-lane time-marching launch over right-hand sides [j_begin, j_begin + n).
@@ -895,7 +926,8 @@ static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
 //   0: one right-hand side per lane, 1024-lane workgroups of 4 x 4 rows, 8 slices;
 //   1: two per lane, 512 lanes, 2 x 4 rows, 8 slices;   2: two per lane, 4 x 2 rows, 8 slices;
 //   3: two per lane, 2 x 4 rows, 16 slices;             4: four per lane, 256 lanes, 2 x 2 rows, 8 slices;
-//   5: two per lane, 256 lanes, 2 x 2 rows, 8 slices;   6: two per lane, 256 lanes, 2 x 2 rows, 16 slices.
+//   5: two per lane, 256 lanes, 2 x 2 rows, 8 slices;   6: two per lane, 256 lanes, 2 x 2 rows, 16 slices;
+//   7: schedule 6 as one persistent launch (512 workgroups walking the items).
 // (256-lane workgroups leave room for two per CU, so one computes while the
 // other waits at its slice barrier.)  Right-hand sides beyond the last full
 // group of a schedule go to schedule 0.
@@ -915,6 +947,7 @@ static void launch_march_sched32(int sched, const Geo &g, const GaugeDev &d, con
             case 4: launch_march_nr<Fmt, 5, 2, 2, 8, 4>(g, d, a, ep, 0, ngrp, s); break;
             case 5: launch_march_nr<Fmt, 5, 2, 2, 8, 2>(g, d, a, ep, 0, ngrp, s); break;
             case 6: launch_march_nr<Fmt, 5, 2, 2, 16, 2>(g, d, a, ep, 0, ngrp, s); break;
+            case 7: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s); break;
             default: launch_march_1<Fmt, 5>(g, d, a, ep, 0, a.nrhs, s); return;
         }
     }

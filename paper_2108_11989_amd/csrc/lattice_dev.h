@@ -210,6 +210,17 @@ __device__ __forceinline__ void row2_from_rows(cx<R> u[9]) {
     u[8] = cj(cmul_sub(u[0], u[4], u[1], u[3]));
 }
 
+// The compressed formats store the SU(3) rows and the quark phase exp(i q
+// theta) apart; the phase is multiplied into the nine entries once per load
+// (9 complex products), so every use of the link -- up to two hops and NR
+// right-hand sides -- is a plain 3x3 product.  s = -1 for the conjugate copy.
+__device__ __forceinline__ void apply_phase(Link<float> &L, float2 e, float s) {
+    const cx<float> ph = {e.x, s * e.y};
+#pragma unroll
+    for (int r = 0; r < 9; r++) L.u[r] = L.u[r] * ph;
+    L.ph = {1.f, 0.f};
+}
+
 struct FmtF64 {
     using R = double;
     static __device__ __forceinline__ void load(const GaugeDev &d, const Geo &g, int p, int mu, int h, double s,
@@ -238,10 +249,9 @@ struct FmtF32 {
         L.u[4] = {a2.x, s * a2.y};
         L.u[5] = {a2.z, s * a2.w};
         row2_from_rows(L.u);
-        const float2 e = d.phase32[(long)(p * 4 + mu) * g.Vh + h];
-        L.ph = {e.x, s * e.y};
+        apply_phase(L, d.phase32[(long)(p * 4 + mu) * g.Vh + h], s);
     }
-    static constexpr bool has_phase = true;
+    static constexpr bool has_phase = false;
 };
 
 struct FmtBF16 {
@@ -258,10 +268,9 @@ struct FmtBF16 {
         L.u[4] = {bf_lo(b.x), s * bf_hi(b.x)};
         L.u[5] = {bf_lo(b.y), s * bf_hi(b.y)};
         row2_from_rows(L.u);
-        const float2 e = d.phase32[i];
-        L.ph = {e.x, s * e.y};
+        apply_phase(L, d.phase32[i], s);
     }
-    static constexpr bool has_phase = true;
+    static constexpr bool has_phase = false;
 };
 
 // g = V h (DAG = false) or V^H h (DAG = true) for the two spin rows of a half spinor.

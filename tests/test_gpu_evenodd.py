@@ -3,8 +3,10 @@ the oracle (mass-reweighting section: D_hat = D_ee - D_eo D_oo^{-1} D_oe,
 W_eo = |det D_oo(m') D_oo(m)^{-1}|^{1/2}).
 
 * FP64 D_hat and Q_hat element-wise against oracle.evenodd.apply_dhat,
-  max |diff| <= 1e-13 max |ref| (two applications of the operator and a 6x6
-  inverse: a few ulp of the largest term);
+  max |diff| <= max(1e-13, 50 eps kappa) max |ref|, kappa the largest
+  condition number of the odd-site blocks (4+m) + SW: two applications of
+  the operator and a 6x6 inverse whose forward error grows with kappa (at
+  4+m = 0.1 the blocks are nearly singular);
 * FP32 forms against the oracle in its link-emulation mode, <= 5e-6 (FP32
   arithmetic over the two hops and the FP32-rounded inverse blocks);
 * log W_eo against the oracle's per-site determinants, <= 1e-12 relative
@@ -63,14 +65,18 @@ def test_dhat_fp64_matches_oracle(case):
     par = evenodd.parity_sites(T, L)
     ev = par == 0
     psi = synth.random_spinor(T, L, seed + 50, nrhs=2)
+    od = ~ev
     for m0 in (-0.45, 0.3, -3.9):
+        kappa = float(np.max(np.linalg.cond(op.local_term(m0)[od])))
+        tol = max(1e-13, 50 * 2.2e-16 * kappa)
+        print(f"  m0 {m0}: largest odd-block condition number {kappa:.2e}, tolerance {tol:.1e}", flush=True)
         for gamma5 in (False, True):
             out = _even_apply(g, psi, m0, cstar.FP64, gamma5, nrhs=2)
             for j in range(2):
                 pe = psi[j].reshape(-1, 12)[ev].reshape(-1)
                 ref = evenodd.apply_dhat(op, pe, m0, gamma5).reshape(-1, 12)
                 got = out[j].reshape(-1, 12)
-                assert np.abs(got[ev] - ref).max() <= 1e-13 * np.abs(ref).max(), (m0, gamma5, j)
+                assert np.abs(got[ev] - ref).max() <= tol * np.abs(ref).max(), (m0, gamma5, j)
                 assert np.abs(got[~ev]).max() == 0.0
     g.close()
 
