@@ -266,6 +266,29 @@ cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cs
                            int *sign_out, cstar_sign_report *report);
 
 /*
+ * W_sgn over an ensemble (paper, sign-of-the-Pfaffian section and summary:
+ * the sign of the Pfaffian is a reweighting factor of every configuration,
+ * the product over the quark flavours).  For each configuration c < n_cfg
+ * and flavour f < n_flv: the sign of pf[C T D(m_target[f])] for the field
+ * (su3[c], theta[c]) with charge charges[f] and the other parameters of base
+ * (base->q is ignored), by pfaffian_sign with opts; one GPU, in turn, a
+ * handle created and destroyed per (configuration, flavour).  A flavour
+ * equal to an earlier one (same charge and mass) reuses its sign.
+ * su3[c], theta[c]: as in cstar_gauge_create (host, or device with
+ * src_on_device).  sign_out: host [n_cfg][n_flv], +1 / -1 (0 where
+ * undecidable); product_out: host [n_cfg], the product over flavours;
+ * seconds_out: nullable host [n_cfg].  Synchronous.
+ * Errors: EINVAL; EAMBIG (some sign undecidable: the other entries are
+ * valid); the first other error of a creation or a sign, with its
+ * configuration and flavour in the message (outputs of later
+ * configurations unset).
+ */
+cstar_status cstar_sign_ensemble(const cstar_params *base, int n_cfg, const double *const *su3,
+                                 const double *const *theta, int src_on_device, int n_flv, const double *charges,
+                                 const double *m_target, const cstar_sign_opts *opts, int *sign_out, int *product_out,
+                                 double *seconds_out);
+
+/*
  * Host logic of pfaffian_sign over any eigenvalue provider (the same driver
  * pfaffian_sign uses; a provider may be a test double).  provider(ctx, m, k,
  * evals, errs) must fill the k eigenvalues of Q(m) smallest in modulus, one

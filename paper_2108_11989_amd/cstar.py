@@ -109,6 +109,9 @@ def lib():
         L.cstar_sign_driver.argtypes = [PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ip, ctypes.POINTER(SignReport)]
         L.cstar_clover_norm_max.argtypes = [vp, dp]
+        L.cstar_sign_ensemble.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(dp),
+                                          ctypes.POINTER(dp), ctypes.c_int, ctypes.c_int, dp, dp,
+                                          ctypes.POINTER(SignOpts), ip, ip, dp]
         L.cstar_timing_enable.argtypes = [vp, ctypes.c_int]
         L.cstar_timing_read.argtypes = [vp, ctypes.POINTER(ApplyTiming)]
         fp = ctypes.POINTER(ctypes.c_float)
@@ -126,7 +129,7 @@ def lib():
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
-                     "dirac_apply_noalloc", "dirac_eo_apply", "cstar_log_w_eo",
+                     "dirac_apply_noalloc", "dirac_eo_apply", "cstar_log_w_eo", "cstar_sign_ensemble",
                      "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
@@ -286,6 +289,29 @@ class Gauge:
         _check(lib().pfaffian_sign(self.h, _dp(m), len(m), ctypes.byref(o),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep)))
         return out, rep
+
+
+def sign_ensemble(fields, charges, m_target, T, L, csw_su3=1.9, csw_u1=1.0, time_bc=1, k=4, c=1.9,
+                  eig: EigOpts | None = None):
+    """cstar_sign_ensemble over host fields [(su3, theta), ...]: (status, signs [n_cfg, n_flv],
+    products [n_cfg], seconds [n_cfg])."""
+    n = len(fields)
+    keep = [(np.ascontiguousarray(s3, dtype=np.complex128), np.ascontiguousarray(t3, dtype=np.float64))
+            for s3, t3 in fields]
+    P = ctypes.POINTER(ctypes.c_double)
+    su3p = (P * n)(*[_dp(s3.view(np.float64)) for s3, _ in keep])
+    thp = (P * n)(*[_dp(t3) for _, t3 in keep])
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    m = np.ascontiguousarray(m_target, dtype=np.float64)
+    signs = np.zeros((n, len(q)), dtype=np.int32)
+    prods = np.zeros(n, dtype=np.int32)
+    secs = np.zeros(n)
+    opts = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), 0.0)
+    par = Params(int(T), int(L), int(time_bc), 0.0, float(csw_su3), float(csw_u1))
+    ip = ctypes.POINTER(ctypes.c_int)
+    st = lib().cstar_sign_ensemble(ctypes.byref(par), n, su3p, thp, 0, len(q), _dp(q), _dp(m), ctypes.byref(opts),
+                                   signs.ctypes.data_as(ip), prods.ctypes.data_as(ip), _dp(secs))
+    return st, signs, prods, secs
 
 
 NN_PARAMS = 23040

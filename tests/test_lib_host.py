@@ -155,3 +155,14 @@ def test_sign_driver_exclusion_radius_uses_every_error_bound():
     # (with the radius of flow A alone it would jump past the target to 0.6)
     ms = np.array(rep.m[: rep.n_points])
     assert np.isclose(ms[0], 1.5) and np.isclose(ms[1], 0.74)
+
+
+def test_sign_ensemble_rejects_bad_arguments_without_gpu():
+    L = cstar.lib()
+    par = cstar.Params(4, 2, 1, 0.0, 1.9, 1.0)
+    out = np.zeros(2, dtype=np.int32)
+    st = L.cstar_sign_ensemble(ctypes.byref(par), 0, None, None, 0, 1, None, None, None,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), None)
+    assert st == cstar.EINVAL
+    assert b"cstar_sign_ensemble" in L.cstar_last_error()
