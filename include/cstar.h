@@ -266,6 +266,47 @@ cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cs
                            int *sign_out, cstar_sign_report *report);
 
 /*
+ * Rational approximation of the mass-reweighting section (eq. ratapprox):
+ * R(x) = A prod_{i<n} (x + nu2[i]) / (x + mu2[i]) ~ x^{-1/4} on [ra, rb],
+ * optimal of order (n, n) in the uniform relative error, measured as
+ * |log(R(x) x^{1/4})| (Remez exchange).  Outputs: A; nu2[n], mu2[n] (the
+ * paper's nu_i^2 and mu_i^2, ascending, positive); delta, the attained
+ * maximum of |log(R(x) x^{1/4})| on [ra, rb].  Host only, synchronous.
+ * Errors: EINVAL (n outside [1, 32], not 0 < ra < rb), ENOCONV.
+ */
+cstar_status cstar_ratapprox_quartic(int n, double ra, double rb, double *A, double *nu2, double *mu2,
+                                     double *delta);
+
+/*
+ * Mass-reweighting factor (paper, mass-reweighting section, eq. Wmass and the
+ * stochastic estimator after it): W_mass = det[R(Q_hat_m^2) R^{-1}(Q_hat_m'^2)]
+ * for R(x) = A prod_{i<n} (x + nu2[i]) / (x + mu2[i]) (e.g. from
+ * cstar_ratapprox_quartic; A cancels), estimated factor by factor with the
+ * caller's Gaussian sources eta on the even sites:
+ *   W_i ~ (1/nsrc) sum_l exp(-x_il),  x_il = (eta_l, R_i eta_l),
+ *   R_i = (1 + dD S_i)^H (1 + dD S_i) - 1,  dD = D_hat_m' - D_hat_m,
+ *   S_i = (D_hat_m + i g5 nu_i)^{-1} - (D_hat_m' + i g5 mu_i)^{-1}
+ *         - (D_hat_m' + i g5 mu_i)^{-1} dD (D_hat_m + i g5 nu_i)^{-1}
+ * (nu_i = sqrt(nu2[i]), mu_i = sqrt(mu2[i])); the Gaussian average of
+ * exp(-x_i) is det(1 + R_i)^{-1}, the i-th factor of W_mass.  Every inverse
+ * is an FP64 conjugate-gradient solve of Q_hat^2 + s^2 to relative residual
+ * tol followed by one Q_hat.  eta: device, nsrc FP64 even vectors (with
+ * density proportional to exp(-(eta, eta)) for the estimator).  expo: host
+ * [n][nsrc], the x_il; log_w_mass: host, sum_i log((1/nsrc) sum_l exp(-x_il)).
+ * stats: nullable.  Allocates 11 even vectors and a 64 MiB reduction buffer
+ * and frees them before it returns.  Synchronous.
+ * Errors: EINVAL, ENOMEM, ENOCONV (a solve did not converge), EDEVICE.
+ */
+typedef struct {
+    long cg_iterations;  /* over all solves */
+    long eo_applies;     /* applications of D_hat or Q_hat */
+    double seconds;
+} cstar_wmass_stats;
+cstar_status cstar_w_mass(cstar_gauge *g, double m, double m_prime, int n, const double *nu2, const double *mu2,
+                          int nsrc, const void *eta, double tol, double *expo, double *log_w_mass,
+                          cstar_wmass_stats *stats);
+
+/*
  * W_sgn over an ensemble (paper, sign-of-the-Pfaffian section and summary:
  * the sign of the Pfaffian is a reweighting factor of every configuration,
  * the product over the quark flavours).  For each configuration c < n_cfg

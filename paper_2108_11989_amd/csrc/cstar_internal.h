@@ -132,6 +132,9 @@ hipError_t launch_local_inv(const Geo &g, const GaugeDev &d, double m, double2 *
 hipError_t launch_logdet_ratio(const Geo &g, const GaugeDev &d, double m, double mp, double *partial, hipStream_t s);
 hipError_t launch_eo_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const EoArgs &e, hipStream_t s);
 void eo_release(cstar_gauge *g);
+cstar_status eo_apply(cstar_gauge *g, int nrhs, double m0, cstar_prec prec, int gamma5, const void *in, void *out);
+// y += a (g5)^k x on n FP64 even vectors (complex a; g5 when k = 1)
+hipError_t launch_even_axpy(const Geo &g, double are, double aim, int g5, const void *x, void *y, hipStream_t s);
 
 // ---- BLAS on native vectors (kernels_blas.hip) -----------------------------
 // A native FP64 vector is an array of n2 = 24*Vh*... double2 entries (complex numbers);

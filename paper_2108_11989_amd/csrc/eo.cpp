@@ -3,7 +3,7 @@
 // Paper, mass-reweighting section: D_hat = D_ee - D_eo D_oo^{-1} D_oe on the
 // even sites (Q_hat = g5 D_hat), and W_eo = |det[D_oo(m') D_oo(m)^{-1}]|^{1/2},
 // computed exactly.  The handle keeps the inverse blocks of (4+m) + SW on the
-// odd sites for the last mass used, and the odd-site scratch vectors.
+// odd sites for the last two masses used, and the odd-site scratch vectors.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -15,10 +15,17 @@
 
 namespace cstar {
 namespace {
-struct EoState {
+// Inverse blocks of (4+m) + SW on the odd sites for the two masses used last
+// (the mass-reweighting factor alternates between m and m').
+struct InvSlot {
     double m = NAN;
     double2 *inv64 = nullptr;
     float4 *inv32 = nullptr;
+    long stamp = 0;
+};
+struct EoState {
+    InvSlot slot[2];
+    long clock = 0;
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
     double *partial = nullptr;
@@ -29,19 +36,25 @@ EoState *state(cstar_gauge *g) {
     return (EoState *)g->eo;
 }
 
-cstar_status ensure_inverse(cstar_gauge *g, EoState *e, double m) {
+cstar_status ensure_inverse(cstar_gauge *g, EoState *e, double m, InvSlot **out) {
     const long Vh = g->geo.Vh;
-    if (!e->inv64) {
-        if (hipMalloc(&e->inv64, sizeof(double2) * 36 * Vh) != hipSuccess ||
-            hipMalloc(&e->inv32, sizeof(float4) * 18 * Vh) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CSTAR_ENOMEM, "even-odd: device allocation failed");
+    InvSlot *s = nullptr;
+    for (InvSlot &c : e->slot)
+        if (c.m == m) s = &c;
+    if (!s) {
+        s = e->slot[0].stamp <= e->slot[1].stamp ? &e->slot[0] : &e->slot[1];
+        if (!s->inv64) {
+            if (hipMalloc(&s->inv64, sizeof(double2) * 36 * Vh) != hipSuccess ||
+                hipMalloc(&s->inv32, sizeof(float4) * 18 * Vh) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CSTAR_ENOMEM, "even-odd: device allocation failed");
+            }
         }
+        CSTAR_HIP(launch_local_inv(g->geo, g->d, m, s->inv64, s->inv32, g->stream));
+        s->m = m;
     }
-    if (e->m != m) {
-        CSTAR_HIP(launch_local_inv(g->geo, g->d, m, e->inv64, e->inv32, g->stream));
-        e->m = m;
-    }
+    s->stamp = ++e->clock;
+    *out = s;
     return CSTAR_OK;
 }
 }  // namespace
@@ -49,12 +62,40 @@ cstar_status ensure_inverse(cstar_gauge *g, EoState *e, double m) {
 void eo_release(cstar_gauge *g) {
     EoState *e = (EoState *)g->eo;
     if (!e) return;
-    if (e->inv64) (void)hipFree(e->inv64);
-    if (e->inv32) (void)hipFree(e->inv32);
+    for (InvSlot &c : e->slot) {
+        if (c.inv64) (void)hipFree(c.inv64);
+        if (c.inv32) (void)hipFree(c.inv32);
+    }
     if (e->tmp) (void)hipFree(e->tmp);
     if (e->partial) (void)hipFree(e->partial);
     delete e;
     g->eo = nullptr;
+}
+
+// D_hat(m0) (Q_hat with gamma5) on nrhs even vectors, as dirac_eo_apply (no argument checks).
+cstar_status eo_apply(cstar_gauge *g, int nrhs, double m0, cstar_prec prec, int gamma5, const void *in, void *out) {
+    const size_t half = cstar_spinor_bytes(g, prec) / 2;
+    EoState *e = state(g);
+    if (!e) return fail(CSTAR_ENOMEM, "dirac_eo_apply: host allocation failed");
+    InvSlot *sl = nullptr;
+    cstar_status st = ensure_inverse(g, e, m0, &sl);
+    if (st) return st;
+    const size_t need = 2 * half * nrhs;
+    if (e->tmp_bytes < need) {
+        CSTAR_HIP(hipStreamSynchronize(g->stream));
+        if (e->tmp) (void)hipFree(e->tmp);
+        e->tmp = nullptr;
+        e->tmp_bytes = 0;
+        if (hipMalloc(&e->tmp, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CSTAR_ENOMEM, "dirac_eo_apply: device allocation failed");
+        }
+        e->tmp_bytes = need;
+    }
+    EoArgs a{in, e->tmp, out, (long)half, (long)(2 * half), (long)half, nrhs, m0, gamma5 ? 1 : 0,
+             prec == CSTAR_FP64 ? (const void *)sl->inv64 : (const void *)sl->inv32};
+    CSTAR_HIP(launch_eo_apply(g->geo, g->d, prec, a, g->stream));
+    return CSTAR_OK;
 }
 
 }  // namespace cstar
@@ -73,26 +114,7 @@ cstar_status dirac_eo_apply(cstar_gauge *g, int nrhs, double m0, cstar_prec prec
     const size_t half = cstar_spinor_bytes(g, prec) / 2;
     const char *ib = (const char *)in, *ob = (const char *)out;
     if (ib < ob + half * nrhs && ob < ib + half * nrhs) return fail(CSTAR_EINVAL, "dirac_eo_apply: in and out overlap");
-    EoState *e = state(g);
-    if (!e) return fail(CSTAR_ENOMEM, "dirac_eo_apply: host allocation failed");
-    cstar_status st = ensure_inverse(g, e, m0);
-    if (st) return st;
-    const size_t need = 2 * half * nrhs;
-    if (e->tmp_bytes < need) {
-        CSTAR_HIP(hipStreamSynchronize(g->stream));
-        if (e->tmp) (void)hipFree(e->tmp);
-        e->tmp = nullptr;
-        e->tmp_bytes = 0;
-        if (hipMalloc(&e->tmp, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CSTAR_ENOMEM, "dirac_eo_apply: device allocation failed");
-        }
-        e->tmp_bytes = need;
-    }
-    EoArgs a{in, e->tmp, out, (long)half, (long)(2 * half), (long)half, nrhs, m0, gamma5 ? 1 : 0,
-             prec == CSTAR_FP64 ? (const void *)e->inv64 : (const void *)e->inv32};
-    CSTAR_HIP(launch_eo_apply(g->geo, g->d, prec, a, g->stream));
-    return CSTAR_OK;
+    return eo_apply(g, nrhs, m0, prec, gamma5, in, out);
 }
 
 cstar_status cstar_log_w_eo(cstar_gauge *g, double m, double m_prime, double *log_w_eo) {

@@ -304,6 +304,28 @@ __global__ void k_logdet_ratio(Geo g, const double2 *__restrict__ clov64, double
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// y += a (g5)^k x on one FP64 even vector ([12][Vh][2] double2: component c, spin c/3)
+__global__ void k_even_axpy(Geo g, double are, double aim, int g5, const double2 *__restrict__ x,
+                            double2 *__restrict__ y) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n = 24L * g.Vh;
+    if (e >= n) return;
+    const int comp = (int)(e / (2L * g.Vh));
+    const double s = (g5 && comp >= 6) ? -1.0 : 1.0;
+    const double2 v = x[e];
+    double2 w = y[e];
+    w.x += s * (are * v.x - aim * v.y);
+    w.y += s * (are * v.y + aim * v.x);
+    y[e] = w;
+}
+
+hipError_t launch_even_axpy(const Geo &g, double are, double aim, int g5, const void *x, void *y, hipStream_t s) {
+    const long n = 24L * g.Vh;
+    hipLaunchKernelGGL(k_even_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, are, aim, g5,
+                       (const double2 *)x, (double2 *)y);
+    return hipGetLastError();
+}
+
 int eo_pairs_blocks(const Geo &g) { return (2 * g.Vh + 255) / 256; }
 
 hipError_t launch_local_inv(const Geo &g, const GaugeDev &d, double m, double2 *inv64, float4 *inv32, hipStream_t s) {

@@ -56,6 +56,10 @@ class LbarStats(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class WmassStats(ctypes.Structure):
+    _fields_ = [("cg_iterations", ctypes.c_long), ("eo_applies", ctypes.c_long), ("seconds", ctypes.c_double)]
+
+
 class SignOpts(ctypes.Structure):
     _fields_ = [("eig", EigOpts), ("k", ctypes.c_int), ("c", ctypes.c_double), ("m_max", ctypes.c_double)]
 
@@ -109,6 +113,9 @@ def lib():
         L.cstar_sign_driver.argtypes = [PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ip, ctypes.POINTER(SignReport)]
         L.cstar_clover_norm_max.argtypes = [vp, dp]
+        L.cstar_w_mass.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, ctypes.c_int, vp,
+                                   ctypes.c_double, dp, dp, ctypes.POINTER(WmassStats)]
+        L.cstar_ratapprox_quartic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.cstar_sign_ensemble.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(dp),
                                           ctypes.POINTER(dp), ctypes.c_int, ctypes.c_int, dp, dp,
                                           ctypes.POINTER(SignOpts), ip, ip, dp]
@@ -130,6 +137,7 @@ def lib():
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
                      "dirac_apply_noalloc", "dirac_eo_apply", "cstar_log_w_eo", "cstar_sign_ensemble",
+                     "cstar_ratapprox_quartic", "cstar_w_mass",
                      "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
@@ -255,6 +263,20 @@ class Gauge:
         _check(lib().cstar_log_w_eo(self.h, float(m), float(m_prime), ctypes.byref(v)))
         return v.value
 
+    def w_mass(self, m, m_prime, nu2, mu2, eta, tol=1e-12):
+        """cstar_w_mass with device sources eta (nsrc FP64 even vectors, torch):
+        (log W_mass, exponents [n, nsrc], WmassStats)."""
+        nu2 = np.ascontiguousarray(nu2, dtype=np.float64)
+        mu2 = np.ascontiguousarray(mu2, dtype=np.float64)
+        nsrc = eta.numel() * eta.element_size() // (self.spinor_bytes(FP64) // 2)
+        expo = np.zeros((len(nu2), nsrc))
+        lw = ctypes.c_double()
+        st = WmassStats()
+        _check(lib().cstar_w_mass(self.h, float(m), float(m_prime), len(nu2), _dp(nu2), _dp(mu2), int(nsrc),
+                                  ctypes.c_void_p(eta.data_ptr()), float(tol), _dp(expo), ctypes.byref(lw),
+                                  ctypes.byref(st)))
+        return lw.value, expo, st
+
     def lowest_eigs(self, m0, k, opts: EigOpts | None = None, evecs=None, raise_on_noconv=True):
         ev = np.zeros(k)
         res = np.zeros(k)
@@ -289,6 +311,17 @@ class Gauge:
         _check(lib().pfaffian_sign(self.h, _dp(m), len(m), ctypes.byref(o),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep)))
         return out, rep
+
+
+def ratapprox_quartic(n, ra, rb):
+    """cstar_ratapprox_quartic: (A, nu2[n], mu2[n], delta) of R(x) = A prod (x+nu2)/(x+mu2) ~ x^(-1/4)."""
+    A = ctypes.c_double()
+    d = ctypes.c_double()
+    nu2 = np.zeros(n)
+    mu2 = np.zeros(n)
+    _check(lib().cstar_ratapprox_quartic(int(n), float(ra), float(rb), ctypes.byref(A), _dp(nu2), _dp(mu2),
+                                         ctypes.byref(d)))
+    return A.value, nu2, mu2, d.value
 
 
 def sign_ensemble(fields, charges, m_target, T, L, csw_su3=1.9, csw_u1=1.0, time_bc=1, k=4, c=1.9,
