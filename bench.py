@@ -10,7 +10,9 @@ the wall clock between device synchronisations.
 
 After the timed steps, on the same field: the single-RHS apply in every
 precision, the CPU oracle on a bounded sample, and the time to sign over the
-32-point kappa path for the mixed-precision, plain FP64 and learned forms --
+32-point kappa path for the mixed-precision, plain FP64 and learned forms,
+and for the mixed form in the paper's order (step A upward from the target
+with lambda_bar by the power method on Q^-2, then step B) --
 each only while the wall-clock budget allows (skipped legs are named in the
 output).
 
@@ -323,8 +325,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16, help="right-hand sides (and masses) of the block step")
     ap.add_argument("--budget-s", type=float, default=480.0,
                     help="wall-clock budget from process start; optional legs that would exceed it are skipped")
-    ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned",
-                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned; 'none')")
+    ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned,stepa",
+                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned, stepa; "
+                         "'none')")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=0, help="eigensolver block size (0: 2k + max(8, k))")
@@ -452,7 +455,7 @@ def main():
     signs = {}
     inner = {"bf16": cstar.FP32_BF16LINKS, "fp64": cstar.FP64}
 
-    def one_sign(name, form, net=None):
+    def one_sign(name, form, net=None, step_a=False):
         gg = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
         if net is not None:
             net.attach(gg)
@@ -460,7 +463,7 @@ def main():
                               block=args.block)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        sg, rep = gg.pfaffian_sign(path, k=args.k, eig=opts)
+        sg, rep = gg.pfaffian_sign(path, k=args.k, eig=opts, step_a_power=step_a)
         s_ = time.perf_counter() - t1
         gg.close()
         signs[name] = {"s_per_sign": s_, "applies": rep.applies, "mass_points_solved": rep.n_points,
@@ -480,6 +483,10 @@ def main():
         one_sign("learned_mixed", "bf16", net)
         signs["learned_mixed"]["train"] = info
         net.close()
+    if "stepa" in legs and have(1.5 * s_mixed + 30, "sign mixed_step_a"):
+        # the paper's order: step A upward from the target with lambda_bar by the power method
+        # on Q^-2, the block solver only above where step A stops
+        one_sign("mixed_step_a", "bf16", step_a=True)
     if len({v["signs"] for v in signs.values()}) > 1:
         log("[bench] WARNING: the forms disagree on the signs")
 

@@ -233,6 +233,11 @@ typedef struct {
     double c;            /* step-A factor, slightly below 2 (paper); 0 = 1.9 */
     double m_max;        /* mass above which no crossing is possible; <= 0: computed
                             from the largest clover norm on the handle */
+    int step_a_power;    /* 1: step A upward from the lowest path mass with lambda_bar
+                            from q_lambda_bar_power (the paper's order), the block
+                            solver only above where step A stops; 0: the block solver
+                            from m_max down */
+    double lbar_tol;     /* relative accuracy of lambda_bar in step A (0 = 1e-3) */
 } cstar_sign_opts;
 
 typedef struct {
@@ -339,6 +344,23 @@ cstar_status cstar_sign_ensemble(const cstar_params *base, int n_cfg, const doub
 typedef int (*cstar_eig_provider)(void *ctx, double m, int k, double *evals, double *errs);
 cstar_status cstar_sign_driver(cstar_eig_provider provider, void *ctx, const double *m_path, int n,
                                int k, double c, double m_max, int *sign_out, cstar_sign_report *report);
+
+/*
+ * Host logic of pfaffian_sign with step_a_power = 1, over any providers
+ * (paper, sign-of-the-Pfaffian section, step A): from the lowest path mass
+ * upwards, m <- m + c (lambda_bar(m) - err(m)), where lbar(ctx, m, &lb,
+ * &err) gives lambda_bar(m) = min |lambda(Q(m))| and a rigorous error bound
+ * (return 0; nonzero = failure, reported as ENOCONV).  Past m_max every
+ * path point has sign +1.  When lambda_bar decreases, or two consecutive
+ * exclusion intervals do not overlap, the range up to the previous step-A
+ * mass is crossing-free, and cstar_sign_driver with provider decides the
+ * sign there and at the path points above it (step B).  Errors as
+ * cstar_sign_driver.
+ */
+typedef int (*cstar_lbar_provider)(void *ctx, double m, double *lambda_bar, double *err);
+cstar_status cstar_sign_driver_a(cstar_lbar_provider lbar, cstar_eig_provider provider, void *ctx,
+                                 const double *m_path, int n, int k, double c, double m_max, int *sign_out,
+                                 cstar_sign_report *report);
 
 /*
  * Kernel timing of the Dirac-apply launches issued on this handle (by

@@ -259,7 +259,21 @@ struct GpuProvider {
     long applies = 0, nn_applies = 0;
     int fallbacks = 0;
     cstar_status last = CSTAR_OK;
+    double lbar_tol = 1e-3;
+    int lbar_calls = 0;
 };
+// lambda_bar for step A by the power method on Q^-2 (q_lambda_bar_power)
+int gpu_lbar(void *ctx, double m, double *lb, double *err) {
+    GpuProvider *p = (GpuProvider *)ctx;
+    cstar_lbar_opts lo{};
+    lo.tol = p->lbar_tol;
+    cstar_lbar_stats st{};
+    cstar_status s = q_lambda_bar_power(p->g, m, &lo, lb, err, &st);
+    p->applies += st.applies_fp64;
+    p->lbar_calls++;
+    p->last = s;
+    return s == CSTAR_OK ? 0 : 1;
+}
 int gpu_provider(void *ctx, double m, int k, double *evals, double *errs) {
     GpuProvider *p = (GpuProvider *)ctx;
     cstar_eig_stats st{};
@@ -285,7 +299,10 @@ cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cs
     // non-negative Hermitian part); the margin keeps the top point off the bound
     const double m_max = opts->m_max > 0 ? opts->m_max : g->clover_norm_max * 1.001 + 1e-3;
     const int k = opts->k > 0 ? opts->k : 4;
-    cstar_status st = sign_driver(gpu_provider, &prov, m_path, n, k, c, m_max, sign_out, report);
+    prov.lbar_tol = opts->lbar_tol > 0 ? opts->lbar_tol : 1e-3;
+    cstar_status st = opts->step_a_power
+                          ? sign_driver_stepa(gpu_lbar, gpu_provider, &prov, m_path, n, k, c, m_max, sign_out, report)
+                          : sign_driver(gpu_provider, &prov, m_path, n, k, c, m_max, sign_out, report);
     if (report) {
         report->applies = prov.applies;
         report->nn_applies = prov.nn_applies;
@@ -298,6 +315,12 @@ cstar_status pfaffian_sign(cstar_gauge *g, const double *m_path, int n, const cs
 cstar_status cstar_sign_driver(cstar_eig_provider provider, void *ctx, const double *m_path, int n, int k, double c,
                                double m_max, int *sign_out, cstar_sign_report *report) {
     return sign_driver(provider, ctx, m_path, n, k, c, m_max, sign_out, report);
+}
+
+cstar_status cstar_sign_driver_a(cstar_lbar_provider lbar, cstar_eig_provider provider, void *ctx,
+                                 const double *m_path, int n, int k, double c, double m_max, int *sign_out,
+                                 cstar_sign_report *report) {
+    return sign_driver_stepa(lbar, provider, ctx, m_path, n, k, c, m_max, sign_out, report);
 }
 
 cstar_status cstar_clover_norm_max(cstar_gauge *g, double *out) {

@@ -102,7 +102,7 @@ hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const 
 // measured with HIP events on the first such launch, or read from the cache
 // file named by CSTAR_TUNE_CACHE; CSTAR_MARCH_SCHEDULE forces one.  launch(s)
 // issues the whole apply with schedule s (every schedule gives the same result).
-constexpr int kMarchSchedules = 8;
+constexpr int kMarchSchedules = 10;
 int march_schedule(const Geo &g, cstar_prec prec, const ApplyArgs &a, hipStream_t s,
                    const std::function<void(int)> &launch);
 // launch_apply on the handle's stream, with event timing when enabled (timing.cpp)
@@ -132,6 +132,8 @@ hipError_t launch_local_inv(const Geo &g, const GaugeDev &d, double m, double2 *
 hipError_t launch_logdet_ratio(const Geo &g, const GaugeDev &d, double m, double mp, double *partial, hipStream_t s);
 hipError_t launch_eo_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const EoArgs &e, hipStream_t s);
 void eo_release(cstar_gauge *g);
+cstar_status sign_driver_stepa(cstar_lbar_provider lbar, cstar_eig_provider prov, void *ctx, const double *m_path,
+                               int n, int k, double c, double m_max, int *sign_out, cstar_sign_report *report);
 cstar_status eo_apply(cstar_gauge *g, int nrhs, double m0, cstar_prec prec, int gamma5, const void *in, void *out);
 // y += a (g5)^k x on n FP64 even vectors (complex a; g5 when k = 1)
 hipError_t launch_even_axpy(const Geo &g, double are, double aim, int g5, const void *x, void *y, hipStream_t s);

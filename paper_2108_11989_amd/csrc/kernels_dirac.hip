@@ -584,16 +584,16 @@ __device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
                                               const typename Prec<Fmt>::V *__restrict__ in,
                                               typename Prec<Fmt>::V *__restrict__ out, long stride, int ngrp,
                                               int gamma5, const double *__restrict__ masses, double mass0,
-                                              const Epi<typename Prec<Fmt>::V> &ep, int item);
+                                              const Epi<typename Prec<Fmt>::V> &ep, int item, int blocked);
 
 template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool EPI, bool PERSIST>
 __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march_nr(
     Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ in, typename Prec<Fmt>::V *__restrict__ out,
     long stride, int ngrp, int gamma5, const double *__restrict__ masses, double mass0,
-    Epi<typename Prec<Fmt>::V> ep, int nitems) {
+    Epi<typename Prec<Fmt>::V> ep, int nitems, int blocked) {
     if constexpr (!PERSIST) {
         march_nr_item<Fmt, LOG2L, RX1, RX2, TB, NR, EPI>(g, d, in, out, stride, ngrp, gamma5, masses, mass0, ep,
-                                                         xcd_tile(gridDim.x));
+                                                         xcd_tile(gridDim.x), blocked);
     } else {
         // persistent: workgroup w stays on XCD w mod 8 and walks that XCD's
         // contiguous range of items (nitems is a multiple of 8) with the
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(RX1 * RX2 * (2 << LOG2L)) void k_apply_march_nr(
         const int per_xcd = nitems >> 3;
         for (int k = w >> 3; k < per_xcd; k += nloc)
             march_nr_item<Fmt, LOG2L, RX1, RX2, TB, NR, EPI>(g, d, in, out, stride, ngrp, gamma5, masses, mass0,
-                                                             ep, x * per_xcd + k);
+                                                             ep, x * per_xcd + k, blocked);
     }
 }
 
@@ -612,7 +612,7 @@ __device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
                                               const typename Prec<Fmt>::V *__restrict__ in,
                                               typename Prec<Fmt>::V *__restrict__ out, long stride, int ngrp,
                                               int gamma5, const double *__restrict__ masses, double mass0,
-                                              const Epi<typename Prec<Fmt>::V> &ep, int item) {
+                                              const Epi<typename Prec<Fmt>::V> &ep, int item, int blocked) {
     using R = typename Prec<Fmt>::R;
     using V = typename Prec<Fmt>::V;
     constexpr int L = 1 << LOG2L;
@@ -623,10 +623,21 @@ __device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
     const int grp = item % ngrp;
     int r_ = item / ngrp;
     if (r_ >= per_grp) return;
-    const int tile2 = r_ % N2;
-    r_ /= N2;
-    const int tile1 = r_ % N1;
-    const int seg = r_ / N1;
+    int tile1, tile2, seg;
+    if (blocked && N1 % 2 == 0 && N2 % 4 == 0) {
+        // consecutive tiles (which run together on one XCD) form 2 x 4 blocks of
+        // tiles in (x1, x2), so more of their faces are shared inside the block
+        const int l = r_ % 8;
+        int b = r_ / 8;
+        tile2 = (b % (N2 / 4)) * 4 + (l & 3);
+        b /= N2 / 4;
+        tile1 = (b % (N1 / 2)) * 2 + (l >> 2);
+        seg = b / (N1 / 2);
+    } else {
+        tile2 = r_ % N2;
+        tile1 = (r_ / N2) % N1;
+        seg = r_ / (N1 * N2);
+    }
     const int lane = threadIdx.x;
     const int c = lane & 1;
     const int x3 = (lane >> 1) & (L - 1);
@@ -871,7 +882,7 @@ static Epi<V> shift_epi(const Epi<V> &ep, long off, int j_begin, bool fp64) {
 
 template <class Fmt, int LOG2L, int RX1, int RX2, int TB, int NR, bool PERSIST = false>
 static void launch_march_nr(const Geo &g, const GaugeDev &d, const ApplyArgs &a, const Epi<typename Prec<Fmt>::V> &ep,
-                            int j_begin, int ngrp, hipStream_t s) {
+                            int j_begin, int ngrp, hipStream_t s, int blocked = 0) {
     using V = typename Prec<Fmt>::V;
     constexpr int LANES = RX1 * RX2 * (2 << LOG2L);
     const long st = a.stride / (long)sizeof(V);
@@ -885,10 +896,12 @@ static void launch_march_nr(const Geo &g, const GaugeDev &d, const ApplyArgs &a,
     const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
     if (e.on)
         hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, true, PERSIST>), dim3(nwg), dim3(LANES), 0,
-                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems);
+                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems,
+                           blocked);
     else
         hipLaunchKernelGGL((k_apply_march_nr<Fmt, LOG2L, RX1, RX2, TB, NR, false, PERSIST>), dim3(nwg), dim3(LANES), 0,
-                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems);
+                           s, g, d, (const V *)a.in + off, (V *)a.out + off, st, ngrp, a.gamma5, m, a.mass0, e, nitems,
+                           blocked);
 }
 
 // Single-RHS-per-lane time-marching launch over right-hand sides [j_begin, j_begin + n).
@@ -927,7 +940,8 @@ static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
 //   1: two per lane, 512 lanes, 2 x 4 rows, 8 slices;   2: two per lane, 4 x 2 rows, 8 slices;
 //   3: two per lane, 2 x 4 rows, 16 slices;             4: four per lane, 256 lanes, 2 x 2 rows, 8 slices;
 //   5: two per lane, 256 lanes, 2 x 2 rows, 8 slices;   6: two per lane, 256 lanes, 2 x 2 rows, 16 slices;
-//   7: schedule 6 as one persistent launch (512 workgroups walking the items).
+//   7: schedule 6 as one persistent launch (512 workgroups walking the items);
+//   8, 9: schedules 6, 7 with the tiles dealt in 2 x 4 blocks.
 // (256-lane workgroups leave room for two per CU, so one computes while the
 // other waits at its slice barrier.)  Right-hand sides beyond the last full
 // group of a schedule go to schedule 0.
@@ -948,6 +962,8 @@ static void launch_march_sched32(int sched, const Geo &g, const GaugeDev &d, con
             case 5: launch_march_nr<Fmt, 5, 2, 2, 8, 2>(g, d, a, ep, 0, ngrp, s); break;
             case 6: launch_march_nr<Fmt, 5, 2, 2, 16, 2>(g, d, a, ep, 0, ngrp, s); break;
             case 7: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s); break;
+            case 8: launch_march_nr<Fmt, 5, 2, 2, 16, 2>(g, d, a, ep, 0, ngrp, s, 1); break;
+            case 9: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s, 1); break;
             default: launch_march_1<Fmt, 5>(g, d, a, ep, 0, a.nrhs, s); return;
         }
     }

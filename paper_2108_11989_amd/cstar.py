@@ -61,7 +61,8 @@ class WmassStats(ctypes.Structure):
 
 
 class SignOpts(ctypes.Structure):
-    _fields_ = [("eig", EigOpts), ("k", ctypes.c_int), ("c", ctypes.c_double), ("m_max", ctypes.c_double)]
+    _fields_ = [("eig", EigOpts), ("k", ctypes.c_int), ("c", ctypes.c_double), ("m_max", ctypes.c_double),
+                ("step_a_power", ctypes.c_int), ("lbar_tol", ctypes.c_double)]
 
 
 class SignReport(ctypes.Structure):
@@ -77,6 +78,8 @@ class ApplyTiming(ctypes.Structure):
 
 PROVIDER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+LBAR_PROVIDER = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double))
 
 _lib = None
 
@@ -113,6 +116,8 @@ def lib():
         L.cstar_sign_driver.argtypes = [PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ip, ctypes.POINTER(SignReport)]
         L.cstar_clover_norm_max.argtypes = [vp, dp]
+        L.cstar_sign_driver_a.argtypes = [LBAR_PROVIDER, PROVIDER, vp, dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, ip, ctypes.POINTER(SignReport)]
         L.cstar_w_mass.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, ctypes.c_int, vp,
                                    ctypes.c_double, dp, dp, ctypes.POINTER(WmassStats)]
         L.cstar_ratapprox_quartic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
@@ -137,7 +142,7 @@ def lib():
         L.cstar_nn_attach.argtypes = [vp, vp]
         for name in ("cstar_gauge_create", "cstar_spinor_pack", "cstar_spinor_unpack", "dirac_apply",
                      "dirac_apply_noalloc", "dirac_eo_apply", "cstar_log_w_eo", "cstar_sign_ensemble",
-                     "cstar_ratapprox_quartic", "cstar_w_mass",
+                     "cstar_ratapprox_quartic", "cstar_w_mass", "cstar_sign_driver_a",
                      "q_lowest_eigs", "q_lambda_bar_power", "pfaffian_sign", "cstar_sign_driver", "cstar_clover_norm_max",
                      "cstar_timing_enable", "cstar_timing_read", "cstar_nn_create", "cstar_nn_get_weights",
                      "cstar_nn_set_weights", "cstar_nn_get_grad", "cstar_nn_zero_grad", "cstar_nn_apply",
@@ -303,11 +308,13 @@ class Gauge:
             _check(status)
         return lam.value, bound.value, st
 
-    def pfaffian_sign(self, m_path, k=4, c=1.9, m_max=0.0, eig: EigOpts | None = None):
+    def pfaffian_sign(self, m_path, k=4, c=1.9, m_max=0.0, eig: EigOpts | None = None, step_a_power=False,
+                      lbar_tol=0.0):
         m = np.ascontiguousarray(np.asarray(m_path, dtype=np.float64))
         out = np.zeros(len(m), dtype=np.int32)
         rep = SignReport()
-        o = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), float(m_max))
+        o = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), float(m_max), int(bool(step_a_power)),
+                     float(lbar_tol))
         _check(lib().pfaffian_sign(self.h, _dp(m), len(m), ctypes.byref(o),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep)))
         return out, rep
@@ -339,7 +346,7 @@ def sign_ensemble(fields, charges, m_target, T, L, csw_su3=1.9, csw_u1=1.0, time
     signs = np.zeros((n, len(q)), dtype=np.int32)
     prods = np.zeros(n, dtype=np.int32)
     secs = np.zeros(n)
-    opts = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), 0.0)
+    opts = SignOpts(eig if eig is not None else eig_opts(), int(k), float(c), 0.0, 0, 0.0)
     par = Params(int(T), int(L), int(time_bc), 0.0, float(csw_su3), float(csw_u1))
     ip = ctypes.POINTER(ctypes.c_int)
     st = lib().cstar_sign_ensemble(ctypes.byref(par), n, su3p, thp, 0, len(q), _dp(q), _dp(m), ctypes.byref(opts),
@@ -428,6 +435,37 @@ class Net:
     @staticmethod
     def detach(gauge: "Gauge"):
         _check(lib().cstar_nn_attach(gauge.h, None))
+
+
+def sign_driver_a(lbar, provider, m_path, k, c, m_max):
+    """Run the library's step-A driver over Python providers lbar(m) -> (lambda_bar, err) and
+    provider(m, k) -> (evals, errs)."""
+    def cb(ctx, m, kk, ev, er):
+        try:
+            e, r = provider(m, kk)
+            for i in range(kk):
+                ev[i] = float(e[i])
+                er[i] = float(r[i])
+            return 0
+        except Exception:
+            return 1
+
+    def cbl(ctx, m, lb, er):
+        try:
+            a, b = lbar(m)
+            lb[0] = float(a)
+            er[0] = float(b)
+            return 0
+        except Exception:
+            return 1
+
+    cbf, cblf = PROVIDER(cb), LBAR_PROVIDER(cbl)
+    m = np.ascontiguousarray(np.asarray(m_path, dtype=np.float64))
+    out = np.zeros(len(m), dtype=np.int32)
+    rep = SignReport()
+    st = lib().cstar_sign_driver_a(cblf, cbf, None, _dp(m), len(m), int(k), float(c), float(m_max),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(rep))
+    return st, out, rep
 
 
 def sign_driver(provider, m_path, k, c, m_max):

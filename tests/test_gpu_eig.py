@@ -126,3 +126,30 @@ def test_single_16_4_eigenvalues_fp32_vs_fp64():
         assert np.all(err <= rm + r64 + 1e-13)
         assert np.all(err <= 1e-10 * np.maximum(np.abs(e64), 1e-3) + rm + r64)
     g.close()
+
+
+@pytest.mark.parametrize("seed,eps", [(13, 1.2), (21, 1.0), (5, 1.4)])
+def test_pfaffian_sign_step_a_power_matches_dense_inertia(seed, eps):
+    """The paper's order: step A upward from the lowest path mass with lambda_bar
+    from the power method on Q^-2, step B (certified counts) above where it
+    stops; on the tiny workload's path and on rough fields with negative signs,
+    every sign equals the dense inertia."""
+    T, L = 4, 2
+    su3, th = synth.make_field(T, L, eps, seed)
+    q = 2 / 3
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    path = np.linspace(-2.0, 0.4, 13)
+    signs, rep = g.pfaffian_sign(path, k=6, eig=cstar.eig_opts(inner=cstar.FP64, tol=1e-10), step_a_power=True)
+    ref = np.array([osign.sign_inertia(op, m) for m in path])
+    print(f"step A: {rep.n_points} masses, signs {signs}", flush=True)
+    assert np.array_equal(signs, ref), (signs, ref)
+    g.close()
+    w, su3, th, q = _tiny()
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    path = synth.kappa_to_m0(w["kappas"])
+    signs, rep = g.pfaffian_sign(path, k=4, eig=cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=1e-10),
+                                 step_a_power=True)
+    assert np.array_equal(signs, [osign.sign_inertia(op, float(m)) for m in path])
+    g.close()

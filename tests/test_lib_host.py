@@ -166,3 +166,57 @@ def test_sign_ensemble_rejects_bad_arguments_without_gpu():
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), None)
     assert st == cstar.EINVAL
     assert b"cstar_sign_ensemble" in L.cstar_last_error()
+
+
+def _lbar(a, s, err=1e-12):
+    def lb(m):
+        return float(np.min(np.abs(a + s * m))), err
+    return lb
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_step_a_driver_on_closed_form_flows(seed):
+    """Step A upward from the lowest path mass, then step B above where it stops:
+    the signs equal the closed-form crossing parities."""
+    a, s = _flow(seed)
+    path = np.linspace(-0.9, 2.5, 9)
+    st, signs, rep = cstar.sign_driver_a(_lbar(a, s), _provider(a, s), path, k=6, c=1.9, m_max=3.0)
+    assert st == cstar.OK, cstar.lib().cstar_last_error()
+    n_top = np.sum(a + s * 3.0 < 0)
+    for m, sg in zip(path, signs):
+        n = np.sum(a + s * m < 0)
+        assert sg == (-1 if (n - n_top) % 2 else 1), (m, n, n_top)
+
+
+def test_step_a_driver_covers_a_gapped_flow_without_eigensolves():
+    """Flows that rise from the target: step A alone reaches m_max (the exclusion
+    intervals cover the range), every sign is +1, and the eigensolver is never called."""
+    a = np.array([0.3, 0.5, 0.9])
+    s = np.array([0.9, 0.7, 0.8])
+    calls = []
+
+    def prov(m, k):
+        calls.append(m)
+        return _provider(a, s)(m, k)
+
+    st, signs, rep = cstar.sign_driver_a(_lbar(a, s), prov, np.linspace(0.0, 1.0, 11), k=3, c=1.9, m_max=4.0)
+    assert st == cstar.OK and np.all(signs == 1)
+    assert calls == []
+    ms = np.array(rep.m[: rep.n_points])
+    # the step-A sequence m_{n+1} = m_n + 1.9 lambda_bar(m_n) from the lowest path mass
+    lb0 = np.min(a)
+    assert np.isclose(ms[0], 0.0) and np.isclose(ms[1], 1.9 * lb0)
+
+
+def test_step_a_driver_hands_over_at_a_decrease():
+    """lambda_bar falls after the first step (a flow crossing above the target):
+    the driver hands the range above the target to step B, which finds the crossing."""
+    a = np.array([-0.5, 1.2])
+    s = np.array([1.0, 0.5])  # first flow crosses zero at m = 0.5
+    path = [0.0, 0.3, 0.8, 1.5]
+    st, signs, rep = cstar.sign_driver_a(_lbar(a, s), _provider(a, s), path, k=2, c=1.9, m_max=3.0)
+    assert st == cstar.OK
+    n_top = np.sum(a + s * 3.0 < 0)
+    ref = [(-1 if (np.sum(a + s * m < 0) - n_top) % 2 else 1) for m in path]
+    assert list(signs) == ref
+    assert ref[0] == -1 and ref[-1] == 1
