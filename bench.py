@@ -35,7 +35,8 @@ HBM_PEAK_GBS = 8000.0
 T_START = time.time()
 
 # sources of the apply kernels; the committed counter summary records their hash
-APPLY_SOURCES = ("paper_2108_11989_amd/csrc/kernels_dirac.hip", "paper_2108_11989_amd/csrc/lattice_dev.h")
+APPLY_SOURCES = ("paper_2108_11989_amd/csrc/kernels_dirac.hip", "paper_2108_11989_amd/csrc/lattice_dev.h",
+                 "paper_2108_11989_amd/csrc/stencil_dev.h", "paper_2108_11989_amd/csrc/tune.cpp")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "apply_traffic_32x32x32x32.md")
 
 
@@ -48,12 +49,12 @@ def apply_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec_name: str, rhs_per_launch: float):
-    """HBM bytes per launch of the apply kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain
-    copy), interpolated linearly in the number of right-hand sides between the
-    measured launch widths; None if the summary is missing or was taken on
-    other kernel sources."""
+def measured_traffic(prec_name: str, rhs_per_launch: int):
+    """HBM bytes per launch of the block step's kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE runs of this bench,
+    each scaled by what the counter reads for a plain copy of known size):
+    the line `traffic <form> <nrhs> <bytes>`; None if the summary is missing,
+    has no line for this launch, or was taken on other kernel sources."""
     try:
         lines = open(TRAFFIC_SUMMARY).read().splitlines()
     except OSError:
@@ -61,12 +62,11 @@ def measured_traffic(prec_name: str, rhs_per_launch: float):
     src = [ln.split()[-1] for ln in lines if ln.startswith("source_sha256:")]
     if not src or src[0] != apply_source_hash():
         return None
-    pts = sorted((float(f[2]), float(f[3])) for f in (ln.split() for ln in lines if ln.startswith("traffic "))
-                 if f[1] == prec_name)
-    if len(pts) < 2:
-        return None
-    (n0, b0), (n1, b1) = pts[0], pts[-1]
-    return b0 + (b1 - b0) * (rhs_per_launch - n0) / (n1 - n0)
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == prec_name and int(f[2]) == int(rhs_per_launch):
+            return float(f[3])
+    return None
 
 
 def log(*a):
@@ -351,6 +351,12 @@ def main():
     ap.add_argument("--inner", default="bf16", choices=["bf16", "fp32", "fp64"], help="filter precision of --sign-path")
     ap.add_argument("--learned", action="store_true", help="--sign-path with the learned preconditioner")
     ap.add_argument("--charges", default="", help="comma-separated indices of the workload's quark charges (default: all)")
+    ap.add_argument("--fp64-rerun", action="store_true",
+                    help="instead of the block step: eigenvalues at --rerun-masses path masses in FP64, mixed and "
+                         "learned forms, errors against FP64 (charge index --charges, default 0)")
+    ap.add_argument("--rerun-masses", type=int, default=4)
+    ap.add_argument("--rerun-signs", action="store_true", help="with --fp64-rerun: also the sign over the path "
+                                                               "in FP64 and mixed precision")
     ap.add_argument("--train-fields", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
@@ -398,6 +404,9 @@ def main():
         return
     if args.sign_path:
         sign_path(args, w, su3_d, th_d, path, nsites2)
+        return
+    if args.fp64_rerun:
+        fp64_rerun(args, w, su3_d, th_d, path)
         return
 
     # ---------------------------------------------------------------- the timed block step
@@ -519,6 +528,59 @@ def main():
         "wall_s": time.time() - T_START,
     }
     print(json.dumps(out), flush=True)
+
+
+def fp64_rerun(args, w, su3_d, th_d, path):
+    """The FP64 GPU rerun as judge: the k lowest eigenvalues at a few masses of
+    the path, solved cold in plain FP64, mixed precision and learned + mixed
+    (network trained on small fields of the workload's distribution), with the
+    error of each form's eigenvalues against the FP64 solve; then, with
+    --rerun-signs, the sign over the whole path in FP64 and in mixed precision."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    q = float(w["q"][int(args.charges or 0)])
+    idx = np.linspace(0, len(path) - 1, args.rerun_masses).round().astype(int)
+    net, info = train_network(args, w, q, float(path[0]))
+    out = {"workload": args.workload, "q": q, "k": args.k, "tol": args.tol, "masses": [], "train": info}
+    forms = (("fp64", cstar.FP64, 0), ("mixed", cstar.FP32_BF16LINKS, 0), ("learned_mixed", cstar.FP32_BF16LINKS, 1))
+    for i in idx:
+        m = float(path[i])
+        row = {"m0": m}
+        for name, prec, nn in forms:
+            g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+            if nn:
+                net.attach(g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, res, st = g.lowest_eigs(m, args.k, cstar.eig_opts(inner=prec, tol=args.tol, max_iter=1000, use_nn=nn))
+            row[name] = {"lambda": [float(x) for x in ev], "resid": [float(x) for x in res],
+                         "s": time.perf_counter() - t0, "applies": st.applies_inner + st.applies_fp64}
+            if nn:
+                cstar.Net.detach(g)
+            g.close()
+        ref = np.array(row["fp64"]["lambda"])
+        for name in ("mixed", "learned_mixed"):
+            row[name]["max_rel_err_vs_fp64"] = float(np.max(np.abs(np.array(row[name]["lambda"]) - ref) / np.abs(ref)))
+        log(f"[bench] rerun m0={m:+.4f}: fp64 {row['fp64']['s']:.1f} s, mixed {row['mixed']['s']:.1f} s "
+            f"(rel err {row['mixed']['max_rel_err_vs_fp64']:.1e}), learned {row['learned_mixed']['s']:.1f} s "
+            f"(rel err {row['learned_mixed']['max_rel_err_vs_fp64']:.1e})")
+        out["masses"].append(row)
+    net.close()
+    if args.rerun_signs:
+        out["signs"] = {}
+        for name, prec in (("mixed", cstar.FP32_BF16LINKS), ("fp64", cstar.FP64)):
+            g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sg, rep = g.pfaffian_sign(path, k=args.k, eig=cstar.eig_opts(inner=prec, tol=args.tol, max_iter=1000))
+            out["signs"][name] = {"s": time.perf_counter() - t0, "signs": "".join("+" if v > 0 else "-" for v in sg),
+                                  "mass_points_solved": rep.n_points, "applies": rep.applies}
+            g.close()
+            log(f"[bench] rerun sign {name}: {out['signs'][name]['s']:.1f} s, {out['signs'][name]['signs']}")
+        out["signs_agree"] = len({v["signs"] for v in out["signs"].values()}) == 1
+    print(json.dumps({"fp64_rerun": out}), flush=True)
 
 
 def sign_path(args, w, su3_d, th_d, path, nsites2):

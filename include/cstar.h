@@ -107,9 +107,15 @@ cstar_status cstar_spinor_unpack(cstar_gauge *g, cstar_prec prec, int nrhs, cons
  * j < nrhs, on the x-doubled lattice (paper: D is the 24V x 24V operator on
  * the quark/antiquark doublet).  in/out: native layout, device, nrhs blocks of
  * cstar_spinor_bytes(prec) each, non-aliasing.  masses: host[nrhs] bare m0.
- * nrhs == 1 runs the single-vector kernel; nrhs > 1 runs the multi-RHS
- * kernel, which reads each link and clover entry once for all right-hand
- * sides.  Asynchronous on the handle's stream.
+ * nrhs == 1 runs the single-vector kernel; nrhs > 1 applies all right-hand
+ * sides in one launch.  At L = 32 in the FP32 forms a lane applies two (or
+ * four) right-hand sides, so each link and clover load serves that many;
+ * the groups of right-hand sides of one lattice tile run together and
+ * re-read the gauge field from L2 or memory.  The schedule is chosen by
+ * timing the candidates on the first launch of a kind (or read from the
+ * file named by CSTAR_TUNE_CACHE); every schedule gives the same bits.
+ * Asynchronous on the handle's stream (the first launch of a kind
+ * synchronises it while it times the schedules).
  */
 cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
                          const void *in, void *out);

@@ -102,7 +102,7 @@ hipError_t launch_apply(const Geo &g, const GaugeDev &d, cstar_prec prec, const 
 // measured with HIP events on the first such launch, or read from the cache
 // file named by CSTAR_TUNE_CACHE; CSTAR_MARCH_SCHEDULE forces one.  launch(s)
 // issues the whole apply with schedule s (every schedule gives the same result).
-constexpr int kMarchSchedules = 10;
+constexpr int kMarchSchedules = 13;
 int march_schedule(const Geo &g, cstar_prec prec, const ApplyArgs &a, hipStream_t s,
                    const std::function<void(int)> &launch);
 // launch_apply on the handle's stream, with event timing when enabled (timing.cpp)

@@ -620,11 +620,21 @@ __device__ __forceinline__ void march_nr_item(const Geo &g, const GaugeDev &d,
     constexpr int LANES = RX1 * RX2 * (2 << LOG2L);
     const int nseg = (g.T + TB - 1) / TB;
     const int per_grp = N1 * N2 * nseg;
-    const int grp = item % ngrp;
-    int r_ = item / ngrp;
-    if (r_ >= per_grp) return;
+    int grp, r_;
+    if (blocked == 2) {
+        // group slowest: an XCD's contiguous range of items is one group's
+        // tiles, so the workgroups in flight on it are neighbouring tiles of
+        // one group and share their face rows in L2
+        grp = item / per_grp;
+        r_ = item - grp * per_grp;
+        if (grp >= ngrp) return;
+    } else {
+        grp = item % ngrp;
+        r_ = item / ngrp;
+        if (r_ >= per_grp) return;
+    }
     int tile1, tile2, seg;
-    if (blocked && N1 % 2 == 0 && N2 % 4 == 0) {
+    if (blocked == 1 && N1 % 2 == 0 && N2 % 4 == 0) {
         // consecutive tiles (which run together on one XCD) form 2 x 4 blocks of
         // tiles in (x1, x2), so more of their faces are shared inside the block
         const int l = r_ % 8;
@@ -941,7 +951,9 @@ static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
 //   3: two per lane, 2 x 4 rows, 16 slices;             4: four per lane, 256 lanes, 2 x 2 rows, 8 slices;
 //   5: two per lane, 256 lanes, 2 x 2 rows, 8 slices;   6: two per lane, 256 lanes, 2 x 2 rows, 16 slices;
 //   7: schedule 6 as one persistent launch (512 workgroups walking the items);
-//   8, 9: schedules 6, 7 with the tiles dealt in 2 x 4 blocks.
+//   8, 9: schedules 6, 7 with the tiles dealt in 2 x 4 blocks;
+//   10, 11, 12: schedules 6, 7, 2 with the groups of right-hand sides slowest
+//   (each XCD runs neighbouring tiles of one group).
 // (256-lane workgroups leave room for two per CU, so one computes while the
 // other waits at its slice barrier.)  Right-hand sides beyond the last full
 // group of a schedule go to schedule 0.
@@ -964,6 +976,9 @@ static void launch_march_sched32(int sched, const Geo &g, const GaugeDev &d, con
             case 7: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s); break;
             case 8: launch_march_nr<Fmt, 5, 2, 2, 16, 2>(g, d, a, ep, 0, ngrp, s, 1); break;
             case 9: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s, 1); break;
+            case 10: launch_march_nr<Fmt, 5, 2, 2, 16, 2>(g, d, a, ep, 0, ngrp, s, 2); break;
+            case 11: launch_march_nr<Fmt, 5, 2, 2, 16, 2, true>(g, d, a, ep, 0, ngrp, s, 2); break;
+            case 12: launch_march_nr<Fmt, 5, 4, 2, 8, 2>(g, d, a, ep, 0, ngrp, s, 2); break;
             default: launch_march_1<Fmt, 5>(g, d, a, ep, 0, a.nrhs, s); return;
         }
     }

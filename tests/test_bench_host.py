@@ -13,16 +13,16 @@ def test_algorithmic_bytes_per_site():
     assert bench.algorithmic_bytes(1, 1, 2, 8) == 192 * 8 + 2 * 256
 
 
-def test_measured_traffic_interpolates_and_checks_the_sources(tmp_path, monkeypatch):
+def test_measured_traffic_reads_the_launch_and_checks_the_sources(tmp_path, monkeypatch):
     f = tmp_path / "traffic.md"
-    f.write_text("text\n```\nsource_sha256: %s\ntraffic bf16 12 1200\ntraffic bf16 20 2000\n"
+    f.write_text("text\n```\nsource_sha256: %s\ntraffic bf16 16 1600\ntraffic bf16 12 1200\n"
                  "traffic fp64 12 5000\n```\n" % bench.apply_source_hash())
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(f))
     assert bench.measured_traffic("bf16", 16) == 1600
     assert bench.measured_traffic("bf16", 12) == 1200
-    assert bench.measured_traffic("fp64", 12) is None  # one width only: no interpolation
+    assert bench.measured_traffic("bf16", 14) is None  # no line for this launch width
     assert bench.measured_traffic("fp32", 12) is None
-    f.write_text("source_sha256: 0000000000000000\ntraffic bf16 12 1200\ntraffic bf16 20 2000\n")
+    f.write_text("source_sha256: 0000000000000000\ntraffic bf16 16 1600\n")
     assert bench.measured_traffic("bf16", 16) is None  # counters taken on other kernel sources
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
     assert bench.measured_traffic("bf16", 16) is None

@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 T, L = 4, 32
-SCHEDULES = range(10)
+SCHEDULES = range(13)
 
 
 @pytest.fixture(scope="module")
