@@ -357,6 +357,18 @@ def main():
     ap.add_argument("--rerun-masses", type=int, default=4)
     ap.add_argument("--rerun-signs", action="store_true", help="with --fp64-rerun: also the sign over the path "
                                                                "in FP64 and mixed precision")
+    ap.add_argument("--c3-train", default="",
+                    help="instead of the block step: train the network on --c3-fields fields of the workload's "
+                         "distribution (seeds 1000.., 4 plain-solver low modes + 4 Gaussian vectors each, streamed, "
+                         "--c3-steps Adam steps per field) and save its FP32 weights (.npy) to this path")
+    ap.add_argument("--c3-eval", default="",
+                    help="instead of the block step: weights (.npy) to judge on --c3-test held-out fields (seeds "
+                         "2000..): plain vs learned mixed-precision eigensolves at the lightest path mass, and the "
+                         "sign over the path on the first of them")
+    ap.add_argument("--c3-fields", type=int, default=64)
+    ap.add_argument("--c3-steps", type=int, default=3)
+    ap.add_argument("--c3-test", type=int, default=8)
+    ap.add_argument("--c3-sign", type=int, default=1, help="with --c3-eval: 0 skips the signs")
     ap.add_argument("--train-fields", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=30)
     args = ap.parse_args()
@@ -377,6 +389,9 @@ def main():
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
     T, L, q = w["T"], w["L"], w["q"][0]
+    if args.c3_train or args.c3_eval:
+        c3(args, w)
+        return
     log(f"[bench] workload {args.workload}: {T}x{L}^3, eps {w['eps']}, seed {w['seed']}, smear {w['smear']}")
     t0 = time.time()
     su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
@@ -581,6 +596,99 @@ def fp64_rerun(args, w, su3_d, th_d, path):
             log(f"[bench] rerun sign {name}: {out['signs'][name]['s']:.1f} s, {out['signs'][name]['signs']}")
         out["signs_agree"] = len({v["signs"] for v in out["signs"].values()}) == 1
     print(json.dumps({"fp64_rerun": out}), flush=True)
+
+
+def c3(args, w):
+    """The learned preconditioner at the workload's own size: trained on many
+    fields of its distribution (streamed: a field, its plain-solver low modes,
+    a few Adam steps, the next field), then judged on held-out fields against
+    the plain solver (same filter, same tolerance)."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, learned, synth
+    T, L, q = w["T"], w["L"], w["q"][0]
+    path = np.asarray(synth.kappa_to_m0(w["kappas"]), dtype=np.float64)
+    m_train = float(path[0])
+
+    def field(seed):
+        su3, th = synth.make_field(T, L, w["eps"], seed, smear_steps=w["smear"], smear_backend="torch",
+                                   exp_backend="torch")
+        return cstar.Gauge(torch.from_numpy(su3).cuda(), torch.from_numpy(th).cuda(), q, synth.CSW_SU3,
+                           synth.CSW_U1)
+
+    out = {"workload": args.workload, "lattice": f"{T}x{L}^3", "q": q, "m0": m_train}
+    if args.c3_train:
+        t0 = time.perf_counter()
+        net = cstar.Net(learned.initial_weights(m_train))
+
+        def progress(i, h):
+            np.save(args.c3_train, net.weights().astype(np.float32))  # a checkpoint after every field
+            log(f"[c3] field {i}: loss {h[0]:.4f} -> {h[-1]:.4f} ({time.perf_counter() - t0:.0f} s)")
+
+        hist = learned.train_online(net, lambda i: field(1000 + i), args.c3_fields, m_train, args.c3_steps, 1e-3,
+                                    seed=7000, log=progress)
+        np.save(args.c3_train, net.weights().astype(np.float32))
+        net.close()
+        out["train"] = {"fields": args.c3_fields, "seeds": [1000, 1000 + args.c3_fields - 1],
+                        "pairs_per_field": 8, "low_modes_per_field": 4, "adam_steps_per_field": args.c3_steps,
+                        "lr": 1e-3, "loss_first_field": [float(x) for x in hist[0]],
+                        "loss_last_field": [float(x) for x in hist[-1]],
+                        "loss_mean_first_8": float(hist[:8].mean()), "loss_mean_last_8": float(hist[-8:].mean()),
+                        "s": time.perf_counter() - t0, "weights": args.c3_train}
+        print(json.dumps({"c3_train": out}), flush=True)
+        return
+    wts = np.load(args.c3_eval, allow_pickle=False)
+    net = cstar.Net(wts.astype(np.float32))
+    solves = []
+    for i in range(args.c3_test):
+        g = field(2000 + i)
+        row = {"seed": 2000 + i}
+        for name, nn in (("plain_mixed", 0), ("learned_mixed", 1)):
+            if nn:
+                net.attach(g)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ev, res_, st = g.lowest_eigs(m_train, args.k, cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=args.tol,
+                                                                         max_iter=1000, use_nn=nn))
+            row[name] = {"s": time.perf_counter() - t1, "iterations": st.iterations,
+                         "applies": st.applies_inner + st.applies_fp64, "nn_applies": st.nn_applies,
+                         "fallback": st.nn_fallback, "lambda": [float(x) for x in ev],
+                         "resid_max": float(np.max(res_))}
+            if nn:
+                cstar.Net.detach(g)
+        a, b = row["plain_mixed"], row["learned_mixed"]
+        row["eigenvalues_agree"] = all(abs(x - y) <= a["resid_max"] + b["resid_max"] + 1e-12
+                                       for x, y in zip(a["lambda"], b["lambda"]))
+        log(f"[c3] test field {2000 + i}: plain {a['s']:.1f} s / {a['applies']} applies, learned {b['s']:.1f} s / "
+            f"{b['applies']} applies + {b['nn_applies']} network, agree {row['eigenvalues_agree']}")
+        solves.append(row)
+        if i == 0 and args.c3_sign:
+            out["sign"] = {}
+            for name, nn in (("plain_mixed", 0), ("learned_mixed", 1)):
+                g2 = field(2000)
+                if nn:
+                    net.attach(g2)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sg, rep = g2.pfaffian_sign(path, k=args.k, eig=cstar.eig_opts(inner=cstar.FP32_BF16LINKS,
+                                                                               tol=args.tol, max_iter=1000,
+                                                                               use_nn=nn))
+                out["sign"][name] = {"s": time.perf_counter() - t1, "applies": rep.applies,
+                                     "nn_applies": rep.nn_applies, "points_solved": rep.n_points,
+                                     "signs": "".join("+" if v > 0 else "-" for v in sg)}
+                if nn:
+                    cstar.Net.detach(g2)
+                g2.close()
+                log(f"[c3] sign {name}: {out['sign'][name]['s']:.1f} s, {out['sign'][name]['signs']}")
+            out["sign"]["agree"] = out["sign"]["plain_mixed"]["signs"] == out["sign"]["learned_mixed"]["signs"]
+        g.close()
+    net.close()
+    tot = {n: {"s": sum(r[n]["s"] for r in solves), "applies": sum(r[n]["applies"] for r in solves)}
+           for n in ("plain_mixed", "learned_mixed")}
+    out.update({"weights": args.c3_eval, "k": args.k, "tol": args.tol, "solves": solves, "totals": tot,
+                "all_agree": all(r["eigenvalues_agree"] for r in solves)})
+    print(json.dumps({"c3_eval": out}), flush=True)
 
 
 def sign_path(args, w, su3_d, th_d, path, nsites2):

@@ -63,3 +63,23 @@ def train(gauges, xs, nvec: int, m0: float, epochs: int, lr: float, seed: int = 
     net = cstar.Net(initial_weights(m0, seed=seed))
     hist = net.train(gauges, xs, nvec, m0, epochs, lr)
     return net, hist
+
+
+def train_online(net, field_fn, n_fields: int, m0: float, steps_per_field: int, lr: float, n_modes: int = 4,
+                 n_gauss: int = 4, seed: int = 0, log=None) -> np.ndarray:
+    """Streaming training, for lattices whose training sets do not fit in device
+    memory together: field i is drawn by field_fn(i) (a Gauge), its n_modes
+    plain-solver low modes and n_gauss Gaussian vectors are formed, the network
+    takes steps_per_field Adam steps on those pairs (its Adam state carries over
+    from field to field), and the field is freed.  Returns the loss of every
+    step, [n_fields][steps_per_field]."""
+    hist = np.zeros((n_fields, steps_per_field))
+    for i in range(n_fields):
+        g = field_fn(i)
+        x = training_vectors(g, m0, n_modes, n_gauss, seed=seed + 10 * i)
+        hist[i] = net.train([g], [x], n_modes + n_gauss, m0, steps_per_field, lr)
+        del x
+        g.close()
+        if log:
+            log(i, hist[i])
+    return hist
