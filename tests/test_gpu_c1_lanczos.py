@@ -10,9 +10,9 @@ The expected values are the oracle's (tests/golden/c1_lanczos_*.json,
 written by tests/golden/make_lanczos_golden.py, which calls only oracle/):
 8x8^3 (about 8 minutes of oracle time on 8 cores) and 16x16^3, the workload's
 own size (about an hour), so they are stored rather than recomputed here.
-This checks in particular that the solver returns the lowest pairs: at both
-sizes the 7th and 8th pairs lie at the bottom of a dense band of
-near-degenerate pairs.
+This checks in particular that the solver returns the lowest pairs and in
+the right order: at both sizes the six lowest pairs form a near-degenerate
+band (within 2e-3 of each other at 8^4, 6e-4 at 16^4).
 """
 import json
 import os
