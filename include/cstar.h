@@ -116,6 +116,8 @@ cstar_status cstar_spinor_unpack(cstar_gauge *g, cstar_prec prec, int nrhs, cons
  * file named by CSTAR_TUNE_CACHE); every schedule gives the same bits.
  * Asynchronous on the handle's stream (the first launch of a kind
  * synchronises it while it times the schedules).
+ * Errors: EINVAL (null pointer, nrhs < 1 or > 4096, a non-finite mass, an
+ * unknown precision, in and out overlapping), EDEVICE.
  */
 cstar_status dirac_apply(cstar_gauge *g, int nrhs, const double *masses, cstar_prec prec, int gamma5,
                          const void *in, void *out);

@@ -167,3 +167,48 @@ def test_clover_norm_bound_is_rigorous():
     b = g.clover_norm_max()
     assert smax <= b <= 3.0 * smax + 1e-12
     g.close()
+
+
+def test_apply_rejects_bad_arguments_before_any_launch():
+    """Empty input, a non-finite mass, aliasing blocks, an unknown precision and
+    too many right-hand sides are refused with EINVAL (no kernel runs)."""
+    _setup()
+    su3, th = synth.make_field(4, 2, 0.3, 0)
+    g = cstar.Gauge(su3, th, 2 / 3)
+    a, b = g.new_native(2, cstar.FP64), g.new_native(2, cstar.FP64)
+    for masses, x, y, prec in (([], a, b, cstar.FP64), ([0.1, np.nan], a, b, cstar.FP64),
+                               ([0.1, np.inf], a, b, cstar.FP64), ([0.1, 0.2], a, a, cstar.FP64),
+                               ([0.1], a, b, 7)):
+        with pytest.raises(cstar.CstarError) as e:
+            g.apply(x, y, masses, prec)
+        assert e.value.status == cstar.EINVAL
+    big_in, big_out = g.new_native(4097, cstar.FP64), g.new_native(4097, cstar.FP64)
+    with pytest.raises(cstar.CstarError) as e:
+        g.apply(big_in, big_out, np.zeros(4097), cstar.FP64)
+    assert e.value.status == cstar.EINVAL
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [cstar.FP64, cstar.FP32_BF16LINKS])
+def test_apply_at_the_largest_width(prec):
+    """4096 right-hand sides (the largest launch) at 4096 masses on the 4x2^3
+    lattice: sampled right-hand sides, the first, the last and a ragged middle
+    one, equal the single-RHS launch bit for bit and the oracle within the
+    form's bound."""
+    _setup()
+    su3, th = synth.make_field(4, 2, 0.3, 0)
+    g = cstar.Gauge(su3, th, 2 / 3)
+    n = 4096
+    masses = np.linspace(-0.5, 2.0, n)
+    psi = synth.random_spinor(4, 2, 123, nrhs=n)
+    out = gpu_apply(g, psi, masses, prec, True)
+    mode = 0 if prec == cstar.FP64 else 2
+    op = odirac.Operator(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, link_mode=mode)
+    tol = 1e-13 if prec == cstar.FP64 else 2e-6
+    for j in (0, 1777, n - 1):
+        single = gpu_apply(g, psi[j:j + 1], masses[j:j + 1], prec, True)[0]
+        assert np.array_equal(out[j], single), j
+        x = psi[j] if prec == cstar.FP64 else psi[j].astype(np.complex64).astype(np.complex128)
+        ref = op.apply(x, masses[j], True)
+        assert _relerr(out[j], ref) <= tol, j
+    g.close()

@@ -85,3 +85,55 @@ def test_apply_32_4_batched_workload_multi_rhs():
     print(f"  FP64: max rel diff {err:.2e}", flush=True)
     assert err < 1e-13
     g.close()
+
+
+def test_apply_64x32_3_paper_scale_multi_rhs():
+    """The paper-scale instance (64x32^3, eps 0.25, seed 4, no smoothing) at
+    its second charge, q = -1/3: one BF16-link launch of 16 right-hand sides at
+    16 masses of the 48-point path (the launch the sign solver issues there);
+    the first and the last output against the oracle's BF16-link emulation
+    (<= 2e-6), and the FP64 form of the first against the exact oracle
+    (<= 1e-13)."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    w = synth.WORKLOADS["paper_64x32^3"]
+    T, L, q = w["T"], w["L"], w["q"][1]
+    print("paper scale: 64x32^3 field", flush=True)
+    su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"])
+    g = cstar.Gauge(su3, th, q, synth.CSW_SU3, synth.CSW_U1)
+    idx = np.linspace(0, len(w["kappas"]) - 1, NRHS).round().astype(int)
+    masses = [float(m) for m in synth.kappa_to_m0(w["kappas"][idx])]
+    psi = synth.random_spinor(T, L, 515151, nrhs=NRHS, dtype=np.complex64)
+
+    print(f"paper scale: BF16-link launch with {NRHS} right-hand sides", flush=True)
+    prec = cstar.FP32_BF16LINKS
+    canon = torch.from_numpy(psi).cuda().contiguous()
+    nin, nout = g.new_native(NRHS, prec), g.new_native(NRHS, prec)
+    g.pack(canon, nin, prec, NRHS)
+    g.apply(nin, nout, masses, prec, True)
+    res = torch.empty_like(canon)
+    g.unpack(nout, res, prec, NRHS)
+    torch.cuda.synchronize()
+    picks = {j: res[j].cpu().numpy().astype(np.complex128) for j in (0, NRHS - 1)}
+    del canon, res, nin, nout
+
+    opb = odirac.Operator(su3, th, q, synth.CSW_SU3, synth.CSW_U1, link_mode=2)
+    for j, out in picks.items():
+        ref = opb.apply(psi[j].astype(np.complex128), masses[j], True)
+        err = _relerr(out, ref)
+        print(f"  rhs {j} (m0 {masses[j]:+.4f}): max rel diff {err:.2e}", flush=True)
+        assert err < 2e-6
+    del opb
+
+    p64 = psi[0].astype(np.complex128)
+    c64 = torch.from_numpy(p64[None]).cuda().contiguous()
+    n64_in, n64_out = g.new_native(1, cstar.FP64), g.new_native(1, cstar.FP64)
+    g.pack(c64, n64_in, cstar.FP64, 1)
+    g.apply(n64_in, n64_out, masses[:1], cstar.FP64, True)
+    r64 = torch.empty_like(c64)
+    g.unpack(n64_out, r64, cstar.FP64, 1)
+    torch.cuda.synchronize()
+    op = odirac.Operator(su3, th, q, synth.CSW_SU3, synth.CSW_U1)
+    err = _relerr(r64[0].cpu().numpy(), op.apply(p64, masses[0], True))
+    print(f"  FP64: max rel diff {err:.2e}", flush=True)
+    assert err < 1e-13
+    g.close()
