@@ -365,6 +365,10 @@ def main():
                     help="instead of the block step: weights (.npy) to judge on --c3-test held-out fields (seeds "
                          "2000..): plain vs learned mixed-precision eigensolves at the lightest path mass, and the "
                          "sign over the path on the first of them")
+    ap.add_argument("--reweight-probe", action="store_true",
+                    help="instead of the block step: the even-odd apply timed in every form (HIP events), W_eo, "
+                         "one W_mass estimate, lambda_bar by the power method and the ensemble driver, at the "
+                         "workload's size (the ensemble on 16^4 fields of its distribution)")
     ap.add_argument("--c3-fields", type=int, default=64)
     ap.add_argument("--c3-steps", type=int, default=3)
     ap.add_argument("--c3-test", type=int, default=8)
@@ -422,6 +426,9 @@ def main():
         return
     if args.fp64_rerun:
         fp64_rerun(args, w, su3_d, th_d, path)
+        return
+    if args.reweight_probe:
+        reweight_probe(args, w, su3_d, th_d, path)
         return
 
     # ---------------------------------------------------------------- the timed block step
@@ -596,6 +603,93 @@ def fp64_rerun(args, w, su3_d, th_d, path):
             log(f"[bench] rerun sign {name}: {out['signs'][name]['s']:.1f} s, {out['signs'][name]['signs']}")
         out["signs_agree"] = len({v["signs"] for v in out["signs"].values()}) == 1
     print(json.dumps({"fp64_rerun": out}), flush=True)
+
+
+def eo_algorithmic_bytes(prec: int, nsites2: int, nrhs: int) -> float:
+    """Minimum HBM bytes of one application of D_hat = D_ee - D_eo D_oo^-1 D_oe
+    in its two passes, per site of the doubled lattice (half of them even):
+    per RHS the even input read by both passes, the odd intermediate written
+    and read, the even output written (five half vectors); the links read by
+    both passes and the odd inverse and even clover blocks once (shared by a
+    site and its conjugate copy):
+      FP64:             5 x 192/2 B per RHS + 2 x (4 x 144)/2 B + 576/2 B
+      FP32 rows:        5 x  96/2 B per RHS + 2 x (4 x  56)/2 B + 288/2 B
+      FP32 + BF16 rows: 5 x  96/2 B per RHS + 2 x (4 x  32)/2 B + 288/2 B"""
+    spin = {0: 192.0, 1: 96.0, 2: 96.0}[prec]
+    links = {0: 4 * 144.0, 1: 4 * 56.0, 2: 4 * 32.0}[prec]
+    clov = {0: 576.0, 1: 288.0, 2: 288.0}[prec]
+    return nsites2 * (5 * spin / 2 * nrhs + 2 * links / 2 + clov / 2)
+
+
+def reweight_probe(args, w, su3_d, th_d, path):
+    """Measurements of the mass-reweighting rows at the workload's size: the
+    even-odd apply (HIP events; bytes as eo_algorithmic_bytes), log W_eo, one
+    W_mass estimate (one Gaussian source, order-8 rational approximation),
+    lambda_bar by the power method against the block solver at the lightest
+    mass, and the ensemble driver on 16^4 fields of the same distribution."""
+    import numpy as np
+    import torch
+
+    from paper_2108_11989_amd import cstar, synth
+    T, L, q = w["T"], w["L"], w["q"][0]
+    nsites2 = 2 * T * L ** 3
+    m = float(path[0])
+    g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
+    out = {"workload": args.workload, "lattice": f"{T}x{L}^3", "q": q, "m0": m, "eo_apply": {}}
+    stream = torch.cuda.current_stream()
+    for prec, name in ((cstar.FP64, "fp64"), (cstar.FP32, "fp32"), (cstar.FP32_BF16LINKS, "bf16")):
+        for nrhs in (1, 16):
+            a, b = g.new_native(nrhs, prec), g.new_native(nrhs, prec)
+            a.normal_()
+            g.eo_apply(a, b, m, prec, True, nrhs)  # first call: the odd inverse blocks
+            torch.cuda.synchronize()
+            reps = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                g.eo_apply(a, b, m, prec, True, nrhs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = eo_algorithmic_bytes(prec, nsites2, nrhs) / (ms * 1e-3) / 1e9
+            out["eo_apply"][f"{name}_{nrhs}"] = {"ms": ms, "algorithmic_GB_s": gbs, "frac_of_8TB_s": gbs / 8000}
+            log(f"[reweight] eo apply {name} nrhs {nrhs}: {ms:.3f} ms, {gbs:.0f} GB/s ({100 * gbs / 8000:.1f} %)")
+            del a, b
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lw = g.log_w_eo(m, m + 0.01)
+    out["log_w_eo"] = {"m_prime": m + 0.01, "value": lw, "s": time.perf_counter() - t0}
+    log(f"[reweight] log W_eo(m, m+0.01) = {lw:.6e} in {out['log_w_eo']['s']:.3f} s")
+    A, nu2, mu2, delta = cstar.ratapprox_quartic(8, 1e-2, 400.0)
+    eta = g.new_native(1, cstar.FP64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    eta.normal_(generator=gen)
+    eta = eta[: eta.numel() // 2].contiguous().mul_(1 / np.sqrt(2.0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lwm, expo, st = g.w_mass(m, m + 0.01, nu2, mu2, eta, tol=1e-10)
+    dt = time.perf_counter() - t0
+    out["w_mass"] = {"n": 8, "range": [1e-2, 400.0], "delta": delta, "nsrc": 1, "tol": 1e-10, "log_w_mass": lwm,
+                     "s": dt, "cg_iterations": st.cg_iterations, "eo_applies": st.eo_applies,
+                     "ms_per_eo_apply": 1e3 * dt / max(1, st.eo_applies)}
+    log(f"[reweight] W_mass: log {lwm:.6e}, {dt:.1f} s, {st.cg_iterations} CG iterations, {st.eo_applies} FP64 "
+        f"even-odd applies ({out['w_mass']['ms_per_eo_apply']:.3f} ms each, all included)")
+    g.close()
+    del eta
+    lb_args = argparse.Namespace(**vars(args))
+    lb_args.lbar_tol = 1e-3
+    out["lambda_bar"] = compare_lambda_bar(lb_args, su3_d, th_d, q, path[:1])
+    fields = [synth.make_field(16, 16, w["eps"], 3000 + i, smear_steps=w["smear"], smear_backend="torch")
+              for i in range(2)]
+    t0 = time.perf_counter()
+    st_e, signs, prods, secs = cstar.sign_ensemble(fields, [2 / 3, -1 / 3], [m, m], 16, 16, k=args.k,
+                                                   eig=cstar.eig_opts(tol=args.tol, max_iter=1000))
+    out["ensemble"] = {"lattice": "16x16^3", "seeds": [3000, 3001], "charges": [2 / 3, -1 / 3], "m_target": m,
+                       "status": int(st_e), "signs": signs.tolist(), "products": prods.tolist(),
+                       "seconds": secs.tolist(), "s": time.perf_counter() - t0}
+    log(f"[reweight] ensemble 2 x 2 at 16^4: signs {signs.tolist()}, {out['ensemble']['s']:.1f} s")
+    print(json.dumps({"reweight_probe": out}), flush=True)
 
 
 def c3(args, w):

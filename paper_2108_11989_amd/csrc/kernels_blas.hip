@@ -5,7 +5,8 @@
 // touched by the elementwise kernels and the precision conversions.
 //
 //  * gram: G[i][j] = sum_n conj(V_i[n]) W_j[n] (FP64 matrix cores), one
-//    partial matrix per wave, then a fixed-order sum (bit-reproducible);
+//    partial matrix per wave, then a fixed-order sum (bit-reproducible); a
+//    single pair of vectors (a dot product) by plain coalesced FMAs instead;
 //  * combine: Out_j = sum_i V_i C[i][j] (block rotation / projection);
 //  * lincomb: y = a x + b y + c z elementwise (real a,b,c), FP64 or FP32;
 //  * precision conversion between the FP64 and FP32 native layouts;
@@ -23,8 +24,11 @@ constexpr int GT = 64;   // max vectors per side of one gram tile
 // lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
 // D[l/16 + 4r][l%16] in register r).  Every wave owns one contiguous range of
 // n and reads its operands straight from memory (16 vectors x 4 consecutive
-// entries per load), writes one partial matrix; the partials are summed in a
-// fixed order afterwards, so the result is bit-reproducible.
+// entries per load), writes one partial matrix, entry e = i nw + j of wave w
+// at partial[e * nwv + w]; the partials of an entry are summed in a fixed
+// order afterwards, so the result is bit-reproducible.  The number of waves
+// grows as the matrix shrinks (as many as the partial buffer holds, at most
+// 8192), so that small Gram matrices still keep enough loads in flight.
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 template <int TI, int TJ>
@@ -82,7 +86,6 @@ __global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, lon
                 cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-vi[a], wr[b], cim[a][b], 0, 0, 0);
             }
     }
-    double2 *P = partial + (long)wv * GT * GT;
 #pragma unroll
     for (int a = 0; a < TI; a++)
 #pragma unroll
@@ -90,26 +93,73 @@ __global__ __launch_bounds__(256) void k_gram(const double2 *__restrict__ V, lon
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int i = a * 16 + kk + 4 * q, j = b * 16 + r;
-                if (i < nv && j < nw) P[i * GT + j] = make_double2(cre[a][b][q], cim[a][b][q]);
+                if (i < nv && j < nw)
+                    partial[(long)(i * nw + j) * nwv + wv] = make_double2(cre[a][b][q], cim[a][b][q]);
             }
 }
 
-__global__ void k_gram_reduce(const double2 *__restrict__ partial, int nblk, int nv, int nw,
-                              double2 *__restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nv * nw) return;
-    const int i = e / nw, j = e % nw;
+// Entry e of the Gram matrix (one workgroup per entry): the nblk partials of
+// e, each thread a fixed strided subset in order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double2 *__restrict__ partial, int nblk,
+                                                     double2 *__restrict__ out) {
+    __shared__ double2 red[256];
+    const int e = blockIdx.x, t = threadIdx.x;
     double sx = 0.0, sy = 0.0;
-    for (int b = 0; b < nblk; b++) {
-        const double2 v = partial[(long)b * GT * GT + i * GT + j];
+    for (int b = t; b < nblk; b += 256) {
+        const double2 v = partial[(long)e * nblk + b];
         sx += v.x;
         sy += v.y;
     }
-    out[e] = make_double2(sx, sy);
+    red[t] = make_double2(sx, sy);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] = make_double2(red[t].x + red[t + w].x, red[t].y + red[t + w].y);
+        __syncthreads();
+    }
+    if (t == 0) out[e] = red[0];
+}
+
+// x^H y for one pair of vectors: consecutive lanes read consecutive entries,
+// FP64 FMAs in a fixed order per lane, a fixed tree per workgroup, one partial
+// per workgroup (reduced by k_gram_reduce as a 1 x 1 matrix).
+constexpr int kDotBlocks = 2048;
+__global__ __launch_bounds__(256) void k_dot1(const double2 *__restrict__ x, const double2 *__restrict__ y, long n,
+                                              double2 *__restrict__ partial) {
+    __shared__ double2 red[256];
+    const int t = threadIdx.x;
+    double sr = 0.0, si = 0.0;
+    const long step = (long)gridDim.x * 256;
+    long i = (long)blockIdx.x * 256 + t;
+    for (; i + step < n; i += 2 * step) {
+        const double2 a0 = x[i], b0 = y[i], a1 = x[i + step], b1 = y[i + step];
+        sr = fma(a0.x, b0.x, fma(a0.y, b0.y, sr));
+        si = fma(a0.x, b0.y, fma(-a0.y, b0.x, si));
+        sr = fma(a1.x, b1.x, fma(a1.y, b1.y, sr));
+        si = fma(a1.x, b1.y, fma(-a1.y, b1.x, si));
+    }
+    if (i < n) {
+        const double2 a0 = x[i], b0 = y[i];
+        sr = fma(a0.x, b0.x, fma(a0.y, b0.y, sr));
+        si = fma(a0.x, b0.y, fma(-a0.y, b0.x, si));
+    }
+    red[t] = make_double2(sr, si);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] = make_double2(red[t].x + red[t + w].x, red[t].y + red[t + w].y);
+        __syncthreads();
+    }
+    if (t == 0) partial[blockIdx.x] = red[0];
 }
 
 int gram_blocks() { return 1024; }
 size_t gram_partial_bytes() { return (size_t)gram_blocks() * GT * GT * sizeof(double2); }
+
+// waves of a Gram launch for an nv x nw matrix: as many as the partial buffer
+// holds, at most 8192, a multiple of 4 (four waves per workgroup)
+static int gram_waves(int nv, int nw) {
+    const long cap = (long)gram_blocks() * GT * GT / ((long)nv * nw);
+    return (int)(std::min<long>(8192, cap) & ~3L);
+}
 
 template <int TI>
 static void launch_gram_ti(int tj, int nblk, hipStream_t s, const double2 *V, long ldv, int nv, const double2 *W,
@@ -126,7 +176,12 @@ static void launch_gram_ti(int tj, int nblk, hipStream_t s, const double2 *V, lo
 hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, long ldw, int nw, long n,
                        double2 *partial, double2 *out_dev, hipStream_t s) {
     if (nv > GT || nw > GT || nv < 1 || nw < 1) return hipErrorInvalidValue;
-    const int nblk = gram_blocks();  // partial matrices = waves of the launch
+    if (nv == 1 && nw == 1) {
+        hipLaunchKernelGGL(k_dot1, dim3(kDotBlocks), dim3(256), 0, s, V, W, n, partial);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(256), 0, s, partial, kDotBlocks, out_dev);
+        return hipGetLastError();
+    }
+    const int nblk = gram_waves(nv, nw);  // partial matrices = waves of the launch
     const int ti = (nv + 15) / 16, tj = (nw + 15) / 16;
     switch (ti) {
         case 1: launch_gram_ti<1>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
@@ -134,7 +189,7 @@ hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, lon
         case 3: launch_gram_ti<3>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
         default: launch_gram_ti<4>(tj, nblk, s, V, ldv, nv, W, ldw, nw, n, partial); break;
     }
-    hipLaunchKernelGGL(k_gram_reduce, dim3((nv * nw + 255) / 256), dim3(256), 0, s, partial, nblk, nv, nw, out_dev);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nv * nw), dim3(256), 0, s, partial, nblk, out_dev);
     return hipGetLastError();
 }
 
