@@ -11,8 +11,12 @@ path).
   (the two launches differ only in the cache policy of the clover loads).
 * The FP64 form on the first input equals the exact oracle, <= 1e-13.
 
-Collected last: it holds the most host memory (about 15 GB) and takes about
-a minute, mostly in the host-side oracle.
+The paper-scale 64x32^3 launch is checked the same way, and the sign over
+the 32^4 path by the driver's two orders (see the tests).
+
+Collected near the end: these tests hold the most host memory (about 30 GB
+for the paper-scale oracle) and take about three minutes, mostly in the
+host-side oracle and the two signs.
 """
 import numpy as np
 import pytest
@@ -137,3 +141,31 @@ def test_apply_64x32_3_paper_scale_multi_rhs():
     print(f"  FP64: max rel diff {err:.2e}", flush=True)
     assert err < 1e-13
     g.close()
+
+
+def test_sign_32_4_batched_workload_two_orders():
+    """The sign over the batched workload's 32-point kappa path (32^4, k = 4,
+    eigenvalue tolerance 1e-8, mixed precision) by the driver's two orders:
+    the default one (m_max first, step A down, certified crossing counts of the
+    block solver's eigenvalues) and the paper's (step A upward from the target
+    with lambda_bar from the power method on Q^-2, then step B above the
+    hand-over).  They decide by different means and must give the same 32
+    signs; the smoothed field is nearly free and its lowest |lambda| at the
+    lightest mass (about 0.336) is far from zero, so every sign is +1."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    w = synth.WORKLOADS["batched_32^4"]
+    T, L, q = w["T"], w["L"], w["q"][0]
+    print("sign 32^4: field", flush=True)
+    su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], smear_backend="torch")
+    path = np.asarray(synth.kappa_to_m0(w["kappas"]), dtype=np.float64)
+    signs = {}
+    for name, step_a in (("default", False), ("step_a", True)):
+        g = cstar.Gauge(torch.from_numpy(su3).cuda(), torch.from_numpy(th).cuda(), q, synth.CSW_SU3, synth.CSW_U1)
+        print(f"sign 32^4: {name} order", flush=True)
+        sg, rep = g.pfaffian_sign(path, k=4, eig=cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=1e-8, max_iter=1000),
+                                  step_a_power=step_a)
+        print(f"  {name}: {rep.n_points} masses solved, {rep.seconds:.1f} s, crossings {rep.n_crossings}", flush=True)
+        signs[name] = sg.copy()
+        g.close()
+    assert np.array_equal(signs["default"], signs["step_a"])
+    assert np.all(signs["default"] == 1)
