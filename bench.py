@@ -125,6 +125,54 @@ def cpu_baseline(su3, th, q, T, L, budget_s=20.0):
                       f"and link table, {t_setup:.1f} s, not counted)"}
 
 
+def cpu_other_configs(budget_s=30.0):
+    """The oracle beside the GPU at the other sizes (bounded samples): FP64
+    applies of Q per second at the single-vector 16^4 and the paper-scale
+    64x32^3 workloads, and the whole sign over the tiny workload's 16-point
+    kappa path by dense inertia on the host against pfaffian_sign on the GPU
+    (each sign at one mass, by the same path)."""
+    import numpy as np
+    import torch
+
+    from oracle import dirac as odirac
+    from oracle import sign as osign
+    from paper_2108_11989_amd import cstar, synth
+    out = {}
+    for name, n_max in (("single_16^4", 40), ("paper_64x32^3", 6)):
+        w = synth.WORKLOADS[name]
+        T, L = w["T"], w["L"]
+        su3, th = synth.make_field(T, L, w["eps"], w["seed"], smear_steps=w["smear"], exp_backend="torch")
+        op = odirac.Operator(su3, th, w["q"][-1])
+        op.links()
+        psi = synth.random_spinor(T, L, 5)
+        n, t0 = 0, time.time()
+        while n < n_max and time.time() - t0 < budget_s / 4:
+            psi = op.apply(psi, -0.3, True)
+            psi /= np.linalg.norm(psi)
+            n += 1
+        dt = time.time() - t0
+        out[name] = {"applies_per_s": n / dt, "sample": f"{n} FP64 oracle applies of Q at {T}x{L}^3"}
+        del op, su3, th, psi
+    w = synth.WORKLOADS["tiny_4x2^3"]
+    su3, th = synth.make_field(w["T"], w["L"], w["eps"], w["seed"])
+    q = w["q"][0]
+    path = np.asarray(synth.kappa_to_m0(w["kappas"]), dtype=np.float64)
+    op = odirac.Operator(su3, th, q)
+    t0 = time.time()
+    ref = [osign.sign_inertia(op, float(m)) for m in path]
+    t_cpu = time.time() - t0
+    g = cstar.Gauge(su3, th, q, synth.CSW_SU3, synth.CSW_U1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sg, rep = g.pfaffian_sign(path, k=4, eig=cstar.eig_opts(tol=1e-10))
+    t_gpu = time.perf_counter() - t0
+    g.close()
+    out["tiny_4x2^3_sign"] = {"cpu_dense_inertia_s": t_cpu, "gpu_pfaffian_sign_s": t_gpu,
+                              "agree": bool(np.array_equal(np.asarray(sg), np.asarray(ref))),
+                              "signs": "".join("+" if v > 0 else "-" for v in ref)}
+    return out
+
+
 def train_network(args, w, q, m_train):
     """The learned preconditioner, trained here on the GPU (library kernels) on
     smoothed 8^4 fields of the workload's distribution (the network is local:
@@ -481,6 +529,13 @@ def main():
         log("[bench] timing the CPU oracle")
         cpu = cpu_baseline(su3, th, q, T, L)
         log(f"[bench] CPU oracle: {cpu['value']:.2f} applies/s on {cpu['threads']} threads ({cpu['cpu_model']})")
+        if have(90, "cpu_other_configs"):
+            cpu["other_configs"] = cpu_other_configs()
+            oc = cpu["other_configs"]
+            log(f"[bench] CPU oracle: {oc['single_16^4']['applies_per_s']:.1f} applies/s at 16^4, "
+                f"{oc['paper_64x32^3']['applies_per_s']:.2f} at 64x32^3; tiny sign path: dense inertia "
+                f"{oc['tiny_4x2^3_sign']['cpu_dense_inertia_s']:.2f} s, GPU "
+                f"{oc['tiny_4x2^3_sign']['gpu_pfaffian_sign_s']:.2f} s, agree {oc['tiny_4x2^3_sign']['agree']}")
 
     # ---------------------------------------------------------------- time to sign, three forms
     signs = {}
