@@ -1,6 +1,6 @@
 """Gauge-covariant preconditioner network, FP64 forward and backward (oracle; test infrastructure only).
 
-The network is not in the paper; it is the learned part of this build, a
+The network is not in the paper; it is the learned part of this library, a
 linear parallel-transport convolution in the style of published
 gauge-equivariant preconditioner networks.  One layer maps Cin channels of
 spinor fields to Cout channels:

@@ -85,7 +85,7 @@ _lib = None
 
 
 def lib():
-    """Load libcstar.so (built by build.py / __graft_entry__.build())."""
+    """Load libcstar.so (built in-tree by paper_2108_11989_amd/build.py)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
