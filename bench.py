@@ -504,6 +504,20 @@ def main():
     traffic = measured_traffic("bf16", args.nrhs) if args.workload == "batched_32^4" else None
     log(f"[bench] {args.steps} steps in {dt * 1e3:.2f} ms; kernel {avg_ms:.3f} ms per launch (HIP events), "
         f"{achieved:.0f} GB/s algorithmic ({100 * achieved / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
+    # after the timed region: 50 launches, each between two HIP events on the
+    # handle's stream (the null stream, torch's current one), for the spread
+    launch_ms = None
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream == 0:
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+        for e0, e1 in evs:
+            e0.record(cur)
+            g.apply(nin, nout, masses, prec, False)
+            e1.record(cur)
+        torch.cuda.synchronize()
+        per = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+        launch_ms = {"n": len(per), "median": per[len(per) // 2], "min": per[0], "max": per[-1]}
+        log(f"[bench] 50 launches one by one: median {launch_ms['median']:.3f} ms, min {launch_ms['min']:.3f} ms")
     del nin, nout
 
     legs = set() if args.legs == "none" else set(args.legs.split(","))
@@ -596,6 +610,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_apply_march (FP32, BF16 links, multi-RHS)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": byts, "avg_launch_ms": avg_ms},
+        "launch_ms": launch_ms,
         "cpu_baseline": cpu,
         "single_rhs": single,
         "s_per_sign": {k_: v["s_per_sign"] for k_, v in signs.items()},
