@@ -45,11 +45,12 @@ def _apply(g, canon, masses, prec, gamma5):
     return res
 
 
+@pytest.mark.parametrize("time_bc", [1, -1])
 @pytest.mark.parametrize("prec", [cstar.FP32_BF16LINKS, cstar.FP32])
-def test_schedules_bitwise_equal_to_single_rhs(field, prec):
+def test_schedules_bitwise_equal_to_single_rhs(field, prec, time_bc):
     assert torch.cuda.is_available(), "GPU tests need a device"
     su3, th = field
-    g = cstar.Gauge(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1)
+    g = cstar.Gauge(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, time_bc=time_bc)
     nmax = 16
     masses = list(np.linspace(-0.4, 1.3, nmax))
     psi = synth.random_spinor(T, L, 77, nrhs=nmax, dtype=np.complex64)
@@ -59,17 +60,48 @@ def test_schedules_bitwise_equal_to_single_rhs(field, prec):
         for sched in SCHEDULES:
             os.environ["CSTAR_MARCH_SCHEDULE"] = str(sched)
             for n in (2, 3, 5, 16):
-                print(f"schedule {sched} nrhs {n} prec {prec}", flush=True)
+                print(f"schedule {sched} nrhs {n} prec {prec} time_bc {time_bc}", flush=True)
                 multi = _apply(g, canon[:n].contiguous(), masses[:n], prec, True)
                 for j in range(n):
                     assert torch.equal(multi[j], singles[j]), (sched, n, j)
     finally:
         os.environ.pop("CSTAR_MARCH_SCHEDULE", None)
     mode = 2 if prec == cstar.FP32_BF16LINKS else 1
-    op = odirac.Operator(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, link_mode=mode)
+    op = odirac.Operator(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, time_bc=time_bc, link_mode=mode)
     j = 5
     ref = op.apply(psi[j].astype(np.complex128), masses[j], True)
     out = singles[j].cpu().numpy().astype(np.complex128)
+    assert np.abs(out - ref).max() <= 2e-6 * np.abs(ref).max()
+    g.close()
+
+
+def test_schedules_on_ragged_time_segments():
+    """T = 20 at L = 32: the 8- and 16-slice segments end in a partial one (20 =
+    16 + 4 = 8 + 8 + 4), with the antiperiodic time phase crossing a segment
+    start; every schedule on a group and a remainder (3 right-hand sides)
+    equals the single-RHS launches bit for bit, and one right-hand side the
+    oracle's BF16-link emulation."""
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    Tr = 20
+    su3, th = synth.make_field(Tr, L, 0.3, 37)
+    g = cstar.Gauge(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, time_bc=-1)
+    prec = cstar.FP32_BF16LINKS
+    masses = [-0.3, 0.2, 1.1]
+    psi = synth.random_spinor(Tr, L, 79, nrhs=3, dtype=np.complex64)
+    canon = torch.from_numpy(psi).cuda().contiguous()
+    singles = [_apply(g, canon[j:j + 1].contiguous(), masses[j:j + 1], prec, True)[0] for j in range(3)]
+    try:
+        for sched in SCHEDULES:
+            os.environ["CSTAR_MARCH_SCHEDULE"] = str(sched)
+            print(f"ragged T: schedule {sched}", flush=True)
+            multi = _apply(g, canon, masses, prec, True)
+            for j in range(3):
+                assert torch.equal(multi[j], singles[j]), (sched, j)
+    finally:
+        os.environ.pop("CSTAR_MARCH_SCHEDULE", None)
+    op = odirac.Operator(su3, th, 2 / 3, synth.CSW_SU3, synth.CSW_U1, time_bc=-1, link_mode=2)
+    ref = op.apply(psi[2].astype(np.complex128), masses[2], True)
+    out = singles[2].cpu().numpy().astype(np.complex128)
     assert np.abs(out - ref).max() <= 2e-6 * np.abs(ref).max()
     g.close()
 
