@@ -583,6 +583,14 @@ def main():
         one_sign("learned_mixed", "bf16", net)
         signs["learned_mixed"]["train"] = info
         net.close()
+        shipped = os.path.join(os.path.dirname(os.path.abspath(cstar.__file__)), "nn_c3_32x32x32x32.npy")
+        if args.workload == "batched_32^4" and os.path.exists(shipped) and have(1.4 * s_mixed + 10,
+                                                                                 "sign learned_c3_mixed"):
+            # the network trained at this workload's size on 64 fields of its distribution
+            net = cstar.Net(np.load(shipped, allow_pickle=False).astype(np.float32))
+            one_sign("learned_c3_mixed", "bf16", net)
+            signs["learned_c3_mixed"]["weights"] = "nn_c3_32x32x32x32.npy (64 fields at 32^4, 3 Adam steps each)"
+            net.close()
     if "stepa" in legs and have(1.5 * s_mixed + 30, "sign mixed_step_a"):
         # the paper's order: step A upward from the target with lambda_bar by the power method
         # on Q^-2, the block solver only above where step A stops
