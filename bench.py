@@ -374,7 +374,7 @@ def main():
     ap.add_argument("--budget-s", type=float, default=480.0,
                     help="wall-clock budget from process start; optional legs that would exceed it are skipped")
     ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned,stepa",
-                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned, stepa; "
+                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned, resid, stepa; "
                          "'none')")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -555,12 +555,12 @@ def main():
     signs = {}
     inner = {"bf16": cstar.FP32_BF16LINKS, "fp64": cstar.FP64}
 
-    def one_sign(name, form, net=None, step_a=False):
+    def one_sign(name, form, net=None, step_a=False, resid=False):
         gg = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
         if net is not None:
             net.attach(gg)
-        opts = cstar.eig_opts(inner=inner[form], tol=args.tol, max_iter=1000, use_nn=int(net is not None),
-                              block=args.block)
+        opts = cstar.eig_opts(inner=inner[form], tol=args.tol, max_iter=1000,
+                              use_nn=2 if resid else int(net is not None), block=args.block)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sg, rep = gg.pfaffian_sign(path, k=args.k, eig=opts, step_a_power=step_a)
@@ -591,6 +591,9 @@ def main():
             one_sign("learned_c3_mixed", "bf16", net)
             signs["learned_c3_mixed"]["weights"] = "nn_c3_32x32x32x32.npy (64 fields at 32^4, 3 Adam steps each)"
             net.close()
+    if "resid" in legs and have(1.2 * s_mixed + 10, "sign mixed_resid"):
+        # the same extra directions as the learned form with M = 1: the residuals themselves
+        one_sign("mixed_resid", "bf16", resid=True)
     if "stepa" in legs and have(1.5 * s_mixed + 30, "sign mixed_step_a"):
         # the paper's order: step A upward from the target with lambda_bar by the power method
         # on Q^-2, the block solver only above where step A stops

@@ -168,7 +168,8 @@ typedef struct {
     int max_iter;            /* outer iterations */
     int block;               /* vectors per block (>= 2k, <= 64; 0 = 2k + max(8, k)) */
     int degree;              /* Chebyshev filter degree (0 = automatic) */
-    int use_nn;              /* 1: learned preconditioner attached to the handle, if any */
+    int use_nn;              /* 1: learned preconditioner attached to the handle, if any;
+                                2: the residuals themselves as extra directions (no network) */
     int warm_start;          /* 1: start from the Ritz block of this handle's previous converged call */
     unsigned long long seed; /* start vectors */
 } cstar_eig_opts;

@@ -110,16 +110,18 @@ struct Ctx {
 
 // Preconditioned residuals of the nr lowest Ritz pairs into R (FP64):
 //   R_j = M (A x_j - theta_j x_j),
-// with the attached network M ~ A^-1 applied in FP32.  For M close to A^-1 on
-// the modes above the wanted ones, M r_j approximates the error of x_j, so
-// these directions complement the Chebyshev-filtered block (a block
-// Davidson / LOBPCG-style correction).
-cstar_status precond_residuals(Ctx &c, const double2 *X, const double2 *AX, const double *theta, int nr, double2 *R) {
+// with the attached network M ~ A^-1 applied in FP32, or M = 1 (the residuals
+// themselves).  For M close to A^-1 on the modes above the wanted ones,
+// M r_j approximates the error of x_j, so these directions complement the
+// Chebyshev-filtered block (a block Davidson / LOBPCG-style correction).
+cstar_status precond_residuals(Ctx &c, const double2 *X, const double2 *AX, const double *theta, int nr, double2 *R,
+                               bool network) {
     const long n = c.w->n;
     CSTAR_HIP(hipMemcpyAsync(R, AX, sizeof(double2) * n * nr, hipMemcpyDeviceToDevice, c.s));
     for (int j = 0; j < nr; j++)
         CSTAR_HIP(launch_lincomb64(2 * n, -theta[j], (const double *)(X + j * n), 1.0, (double *)(R + j * n), 0.0,
                                    nullptr, c.s));
+    if (!network) return CSTAR_OK;
     CSTAR_HIP(launch_to_f32(c.g->geo, nr, R, c.w->F[0], c.s));
     cstar_status st = nn_apply_block(c.g, c.w->F[0], nr);
     if (st) return st;
@@ -384,9 +386,10 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
     if (nb > 64) return fail(CSTAR_EINVAL, "q_lowest_eigs: block must be <= 64");
     int deg = o.degree > 0 ? o.degree : 24;
     const int deg_max = std::max(deg, 800);
-    const bool use_nn = o.use_nn && g->nn;
-    const int nr = use_nn ? std::min(2 * k, nb) : 0;  // preconditioned residuals per iteration
-    if (use_nn && 2 * nb + nr > 128) return fail(CSTAR_EINVAL, "q_lowest_eigs: block too large for use_nn");
+    const bool use_nn = o.use_nn == 1 && g->nn;
+    const bool use_res = o.use_nn == 2;  // the residuals themselves, no network
+    const int nr = (use_nn || use_res) ? std::min(2 * k, nb) : 0;  // (preconditioned) residuals per iteration
+    if (nr > 0 && 2 * nb + nr > 128) return fail(CSTAR_EINVAL, "q_lowest_eigs: block too large for use_nn");
     Workspace *w = nullptr;
     cstar_status st = ws_get(g, nb, nr, &w);
     if (st) return st;
@@ -444,7 +447,7 @@ cstar_status eig_lowest(cstar_gauge *g, double m0, int k, const cstar_eig_opts *
             // ---- learned preconditioner: append M r_j for the 2k wanted Ritz pairs
             int nin = nf;
             if (nr > 0) {
-                st = precond_residuals(c, X, AX, theta.data(), nr, Y + (long)nf * n);
+                st = precond_residuals(c, X, AX, theta.data(), nr, Y + (long)nf * n, use_nn);
                 if (st) return st;
                 nin = nf + nr;
             }

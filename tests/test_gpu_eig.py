@@ -41,6 +41,23 @@ def test_lowest_eigs_tiny_all_kappas(inner):
     g.close()
 
 
+def test_lowest_eigs_with_residual_directions_tiny():
+    """opts.use_nn = 2 (the residuals of the wanted Ritz pairs appended to the
+    filtered block, no network): the same eigenvalues as the dense oracle."""
+    assert torch.cuda.is_available()
+    w, su3, th, q = _tiny()
+    g = cstar.Gauge(su3, th, q)
+    op = odirac.Operator(su3, th, q)
+    for kappa in w["kappas"][::5]:
+        m0 = float(synth.kappa_to_m0(kappa))
+        ref = dense.lowest_abs(osign.pair_spectrum(op, m0), 4)
+        ev, res, st = g.lowest_eigs(m0, 4, cstar.eig_opts(inner=cstar.FP32_BF16LINKS, tol=1e-12, max_iter=400,
+                                                          use_nn=2))
+        assert st.nn_applies == 0 and st.nn_fallback == 0
+        assert np.all(np.abs(ev - ref) <= 1e-10 * np.abs(ref)), (kappa, ev, ref)
+    g.close()
+
+
 @pytest.mark.parametrize("lattice", ["tiny", "4x8^3"])
 @pytest.mark.parametrize("inner", [cstar.FP64, cstar.FP32_BF16LINKS])
 def test_lowest_eigs_returns_eigenvectors(lattice, inner):
