@@ -930,12 +930,38 @@ static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
     const long items = (long)((1 << LOG2L) / RX1) * ((1 << LOG2L) / RX2) * nseg * n;
     const int nwg = (int)((items + 7) / 8 * 8);
     const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
+    const bool one = n == 1;
+    if constexpr (LOG2L <= 4) {
+        // small lattices (L = 8, 16): fewer workgroups than CUs in the default
+        // tiling; 256-lane workgroups marching 2 slices give 16 times as many
+        // (the same arithmetic per site, so the same bits)
+        constexpr int rows_s = march_rows(256, LOG2L);
+        constexpr int RX1s = march_rx1(rows_s), RX2s = rows_s / RX1s;
+        constexpr int TBs = 2;
+        static_assert(RX1s * RX2s * (2 << LOG2L) == 256, "small march tile");
+        if (nwg < 256) {
+            const int nseg_s = (g.T + TBs - 1) / TBs;
+            const long items_s = (long)((1 << LOG2L) / RX1s) * ((1 << LOG2L) / RX2s) * nseg_s * n;
+            const int nwg_s = (int)((items_s + 7) / 8 * 8);
+            auto go_s = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(nwg_s), dim3(256), 0, s, g, d, (const V *)a.in + off,
+                                   (V *)a.out + off, st, n, a.gamma5, m, a.mass0, e);
+            };
+            if (e.on) {
+                if (one) go_s(k_apply_march<Fmt, LOG2L, RX1s, RX2s, TBs, true, true>);
+                else go_s(k_apply_march<Fmt, LOG2L, RX1s, RX2s, TBs, true, false>);
+            } else {
+                if (one) go_s(k_apply_march<Fmt, LOG2L, RX1s, RX2s, TBs, false, true>);
+                else go_s(k_apply_march<Fmt, LOG2L, RX1s, RX2s, TBs, false, false>);
+            }
+            return;
+        }
+    }
     // epilogue compiled in only where used; clover streamed only when one right-hand side reads it
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nwg), dim3(March<Fmt>::lanes), 0, s, g, d, (const V *)a.in + off,
                            (V *)a.out + off, st, n, a.gamma5, m, a.mass0, e);
     };
-    const bool one = n == 1;
     if (e.on) {
         if (one) go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, true>);
         else go(k_apply_march<Fmt, LOG2L, RX1, RX2, TB, true, false>);
