@@ -931,15 +931,17 @@ static void launch_march_1(const Geo &g, const GaugeDev &d, const ApplyArgs &a, 
     const int nwg = (int)((items + 7) / 8 * 8);
     const double *m = a.masses_dev ? a.masses_dev + j_begin : nullptr;
     const bool one = n == 1;
-    if constexpr (LOG2L <= 4) {
-        // small lattices (L = 8, 16): few workgroups per CU in the default
-        // tiling; 256-lane workgroups marching 2 slices give 16 times as many
-        // (the same arithmetic per site, so the same bits).  Used below one
-        // default workgroup per CU, and for the FP32 forms below four (at 16^4
-        // with 16 right-hand sides: 0.157 against 0.175 ms; FP64 is slower)
+    if constexpr (LOG2L <= 5) {
+        // few workgroups per CU in the default tiling: 256-lane workgroups
+        // (2 x 4 rows at L = 16, 4 x 4 at L = 8 marching 2 slices; 2 x 2 rows
+        // marching 16 slices at L = 32) give 4 to 16 times as many, with the
+        // same arithmetic per site, so the same bits.  Used below one default
+        // workgroup per CU, and for the FP32 forms below four (16^4, 16
+        // right-hand sides: 0.157 against 0.175 ms; 32^4, one: 0.206 against
+        // 0.224 ms; FP64 is slower with them)
         constexpr int rows_s = march_rows(256, LOG2L);
         constexpr int RX1s = march_rx1(rows_s), RX2s = rows_s / RX1s;
-        constexpr int TBs = 2;
+        constexpr int TBs = LOG2L == 5 ? 16 : 2;
         static_assert(RX1s * RX2s * (2 << LOG2L) == 256, "small march tile");
         if (nwg < (std::is_same<Fmt, FmtF64>::value ? 256 : 1024)) {
             const int nseg_s = (g.T + TBs - 1) / TBs;
