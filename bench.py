@@ -417,6 +417,10 @@ def main():
                     help="instead of the block step: the even-odd apply timed in every form (HIP events), W_eo, "
                          "one W_mass estimate, lambda_bar by the power method and the ensemble driver, at the "
                          "workload's size (the ensemble on 16^4 fields of its distribution)")
+    ap.add_argument("--ensemble-probe", type=int, default=0,
+                    help="instead of the block step: W_sgn by the ensemble driver over this many fields of the "
+                         "workload's distribution and size (seeds 3000..), flavours q = 2/3 and -1/3, at the "
+                         "lightest path mass")
     ap.add_argument("--c3-fields", type=int, default=64)
     ap.add_argument("--c3-steps", type=int, default=3)
     ap.add_argument("--c3-test", type=int, default=8)
@@ -443,6 +447,9 @@ def main():
     T, L, q = w["T"], w["L"], w["q"][0]
     if args.c3_train or args.c3_eval:
         c3(args, w)
+        return
+    if args.ensemble_probe > 0:
+        ensemble_probe(args, w)
         return
     log(f"[bench] workload {args.workload}: {T}x{L}^3, eps {w['eps']}, seed {w['seed']}, smear {w['smear']}")
     t0 = time.time()
@@ -771,6 +778,34 @@ def reweight_probe(args, w, su3_d, th_d, path):
                        "seconds": secs.tolist(), "s": time.perf_counter() - t0}
     log(f"[reweight] ensemble 2 x 2 at 16^4: signs {signs.tolist()}, {out['ensemble']['s']:.1f} s")
     print(json.dumps({"reweight_probe": out}), flush=True)
+
+
+def ensemble_probe(args, w):
+    """cstar_sign_ensemble over n fields of the workload's distribution and
+    size (drawn with the torch exponentials, host arrays handed to the
+    driver), two flavours, sign at the lightest path mass: signs, flavour
+    products and seconds per configuration."""
+    import numpy as np
+
+    from paper_2108_11989_amd import cstar, synth
+    T, L = w["T"], w["L"]
+    m = float(np.asarray(synth.kappa_to_m0(w["kappas"]), dtype=np.float64)[0])
+    t0 = time.perf_counter()
+    fields = [synth.make_field(T, L, w["eps"], 3000 + i, smear_steps=w["smear"], smear_backend="torch",
+                               exp_backend="torch") for i in range(args.ensemble_probe)]
+    t_fields = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st, signs, prods, secs = cstar.sign_ensemble(fields, [2 / 3, -1 / 3], [m, m], T, L, k=args.k,
+                                                 eig=cstar.eig_opts(tol=args.tol, max_iter=1000))
+    dt = time.perf_counter() - t0
+    out = {"workload": args.workload, "lattice": f"{T}x{L}^3", "configurations": args.ensemble_probe,
+           "seeds": [3000, 3000 + args.ensemble_probe - 1], "charges": [2 / 3, -1 / 3], "m_target": m,
+           "k": args.k, "tol": args.tol, "status": int(st), "signs": signs.tolist(), "products": prods.tolist(),
+           "seconds_per_configuration": secs.tolist(), "s": dt, "s_fields": t_fields,
+           "signs_per_hour": 3600.0 * signs.size / dt}
+    log(f"[ensemble] {args.ensemble_probe} configurations x 2 flavours at {T}x{L}^3: {dt:.1f} s, products "
+        f"{prods.tolist()}, {out['signs_per_hour']:.0f} signs per hour")
+    print(json.dumps({"ensemble_probe": out}), flush=True)
 
 
 def c3(args, w):
