@@ -216,12 +216,12 @@ def compare_lambda_bar(args, su3_d, th_d, q, masses):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lam, bound, st = g.lambda_bar_power(float(m), tol=args.lbar_tol, max_outer=args.lbar_max_outer,
-                                            raise_on_noconv=False)
+                                            raise_on_noconv=False, inner=cstar.FP32_BF16LINKS)
         t_pow = time.perf_counter() - t0
         conv = bound <= args.lbar_tol * lam
         g.close()
         log(f"[bench] lambda_bar at m0={float(m):+.4f}: power {lam:.6f} +- {bound:.1e} in {t_pow:.1f} s "
-            f"({st.applies_fp64} FP64 applies, {st.solves} solves, converged {conv})")
+            f"({st.applies_inner} mixed + {st.applies_fp64} FP64 applies, {st.solves} solves, converged {conv})")
         g = cstar.Gauge(su3_d, th_d, q, synth.CSW_SU3, synth.CSW_U1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -232,7 +232,7 @@ def compare_lambda_bar(args, su3_d, th_d, q, masses):
         r = {"m0": float(m),
              "power": {"lambda_bar": lam, "half_width": bound, "converged": bool(conv), "s": t_pow,
                        "outer": st.outer, "solves": st.solves, "cg_iterations": st.cg_iterations,
-                       "applies_fp64": st.applies_fp64},
+                       "applies_fp64": st.applies_fp64, "applies_inner": st.applies_inner},
              "block": {"k": args.k, "lambda_bar": float(abs(ev[0])), "resid": float(res[0]), "s": t_blk,
                           "iterations": st2.iterations, "applies_inner": st2.applies_inner,
                           "applies_fp64": st2.applies_fp64},

@@ -205,30 +205,39 @@ typedef struct {
     int max_outer;           /* outer steps (0 = 500) */
     int max_cg;              /* CG iterations per inner solve (0 = 20000) */
     unsigned long long seed; /* start vector */
+    cstar_prec inner;        /* inner CG arithmetic: CSTAR_FP64 (default), or an FP32 form: FP32
+                                arithmetic on the FP32-row operator for the solves whose tolerance
+                                is 1e-6 or looser (FP64 for the tighter ones) */
 } cstar_lbar_opts;
 
 typedef struct {
     int outer;               /* outer (power or Chebyshev) steps */
     int solves;              /* inner CG solves of Q^2 x = y */
     long cg_iterations;      /* CG iterations over all solves */
-    long applies_fp64;       /* single-RHS D applications, all in FP64 */
+    long applies_fp64;       /* single-RHS D applications in FP64 */
     double beta;             /* final upper end of the damped interval of Q^-2 (0: none used) */
     double resid_q2;         /* ||Q^2 v - theta v|| of the final unit vector */
     double seconds;          /* wall time of the call */
+    long applies_inner;      /* single-RHS D applications in the FP32 form of opts.inner */
 } cstar_lbar_stats;
 
 /*
  * lambda_bar(m0) = min |lambda(Q(m0))| by the power method with Chebyshev
  * acceleration applied to Q(m0)^-2, as the paper proposes for step A of the
  * sign algorithm (Sec. 3: only the smallest eigenvalue of |Q| is needed);
- * every product with Q^-2 is an FP64 conjugate-gradient solve on Q^2.
+ * every product with Q^-2 is a conjugate-gradient solve on Q^2, in FP64, or
+ * with opts.inner an FP32 form in FP32 arithmetic on the FP32-row operator
+ * while the solve's tolerance is 1e-6 or looser (the Rayleigh quotient and
+ * the residual bound are always FP64, so the inner precision cannot bias
+ * the bound).
  * lambda_bar: host, sqrt(theta) with theta = v^H Q^2 v the final Rayleigh
  * quotient (an upper bound of lambda_bar^2).  bound: nullable host, the
  * half-width of the interval around lambda_bar that holds |lambda| of some
  * eigenvalue of Q, from r = ||Q^2 v - theta v||:
  * max(sqrt(theta) - sqrt(theta - r), sqrt(theta + r) - sqrt(theta)).  That it
  * is the smallest one rests on the iteration's convergence, as in the paper.
- * opts, stats: nullable.  Allocates 8 FP64 vectors on the handle's device and
+ * opts, stats: nullable.  Allocates 8 FP64 vectors (and, with an FP32 inner
+ * form, 5 FP32 vectors and one more FP64 vector) on the handle's device and
  * frees them before it returns.  Synchronous.
  * Errors: EINVAL (bad options), ENOCONV (max_outer reached; the outputs hold
  * the last iterate), ENOMEM, EDEVICE.

@@ -267,9 +267,10 @@ int gpu_lbar(void *ctx, double m, double *lb, double *err) {
     GpuProvider *p = (GpuProvider *)ctx;
     cstar_lbar_opts lo{};
     lo.tol = p->lbar_tol;
+    lo.inner = p->opts.inner;  // the sign's precision: FP64 stays FP64, the mixed forms solve loose CGs in FP32
     cstar_lbar_stats st{};
     cstar_status s = q_lambda_bar_power(p->g, m, &lo, lb, err, &st);
-    p->applies += st.applies_fp64;
+    p->applies += st.applies_fp64 + st.applies_inner;
     p->lbar_calls++;
     p->last = s;
     return s == CSTAR_OK ? 0 : 1;

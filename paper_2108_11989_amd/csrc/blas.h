@@ -13,6 +13,9 @@ hipError_t launch_gram(const double2 *V, long ldv, int nv, const double2 *W, lon
 // O_j = beta O_j + sum_i V_i C[i*ldc + j], nv <= 128, O must not alias V
 hipError_t launch_combine(const double2 *V, long ldv, int nv, const double2 *C_dev, int ldc, double2 *O, long ldo,
                           int no, long n, hipStream_t s, double beta = 0.0);
+// x^H y of two FP32 native vectors of n4 float4 (FP64 accumulation) into out_dev
+hipError_t launch_dot32(const float4 *x, const float4 *y, long n4, double2 *partial, double2 *out_dev,
+                        hipStream_t s);
 hipError_t launch_lincomb64(long nreal, double a, const double *x, double b, double *y, double c, const double *z,
                             hipStream_t s);
 hipError_t launch_lincomb32(long nreal, float a, const float *x, float b, float *y, float c, const float *z,

@@ -151,6 +151,36 @@ __global__ __launch_bounds__(256) void k_dot1(const double2 *__restrict__ x, con
     if (t == 0) partial[blockIdx.x] = red[0];
 }
 
+// x^H y for one pair of FP32 native vectors (float4 = two complex entries),
+// accumulated in FP64 in the same fixed order as k_dot1
+__global__ __launch_bounds__(256) void k_dot1f(const float4 *__restrict__ x, const float4 *__restrict__ y, long n4,
+                                               double2 *__restrict__ partial) {
+    __shared__ double2 red[256];
+    const int t = threadIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (long i = (long)blockIdx.x * 256 + t; i < n4; i += (long)gridDim.x * 256) {
+        const float4 a = x[i], b = y[i];
+        sr = fma((double)a.x, (double)b.x, fma((double)a.y, (double)b.y, sr));
+        si = fma((double)a.x, (double)b.y, fma(-(double)a.y, (double)b.x, si));
+        sr = fma((double)a.z, (double)b.z, fma((double)a.w, (double)b.w, sr));
+        si = fma((double)a.z, (double)b.w, fma(-(double)a.w, (double)b.z, si));
+    }
+    red[t] = make_double2(sr, si);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] = make_double2(red[t].x + red[t + w].x, red[t].y + red[t + w].y);
+        __syncthreads();
+    }
+    if (t == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_dot32(const float4 *x, const float4 *y, long n4, double2 *partial, double2 *out_dev,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_dot1f, dim3(kDotBlocks), dim3(256), 0, s, x, y, n4, partial);
+    hipLaunchKernelGGL(k_gram_reduce, dim3(1), dim3(256), 0, s, partial, kDotBlocks, out_dev);
+    return hipGetLastError();
+}
+
 int gram_blocks() { return 1024; }
 size_t gram_partial_bytes() { return (size_t)gram_blocks() * GT * GT * sizeof(double2); }
 

@@ -19,7 +19,13 @@
 //     theta itself is an upper bound of lambda_bar^2 (Rayleigh quotient).
 // The inner solves are inexact on purpose: their tolerance follows the outer
 // residual (0.01 of it, within [1e-13, 1e-3]), which slows the outer
-// iteration but cannot bias the reported bound.
+// iteration but cannot bias the reported bound.  For the same reason a solve
+// whose tolerance is 1e-6 or looser may run in FP32 arithmetic (opts.inner)
+// on the operator with FP32 link rows, whose difference from the FP64 one
+// (~1e-7 relative) is far below those tolerances -- BF16 rows (~4e-3) would
+// move the eigenvector the iteration converges to, so an FP32 request of
+// either form uses FP32 rows; the tighter solves, and every Rayleigh quotient
+// and residual, stay in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,15 +44,20 @@ struct Power {
     hipStream_t s;
     double m;
     long n;  // complex entries per FP64 vector
+    cstar_prec inner = CSTAR_FP64;
     double2 *partial = nullptr, *gout = nullptr;
-    long applies = 0, cg_iterations = 0;
+    float4 *r32 = nullptr, *p32 = nullptr, *ap32 = nullptr, *tmp32 = nullptr, *x32 = nullptr;  // FP32 inner CG
+    double2 *e = nullptr;   // FP64 correction of an FP32 solution
+    bool fp32_off = false;  // set once an FP32 solve missed its tolerance: FP64 from then on
+    long applies = 0, applies_inner = 0, cg_iterations = 0;
     int solves = 0;
     std::vector<void *> owned;
 
     ~Power() {
         for (void *p : owned) (void)hipFree(p);
     }
-    cstar_status alloc(double2 **p, size_t bytes) {
+    template <class T>
+    cstar_status alloc(T **p, size_t bytes) {
         if (hipMalloc((void **)p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CSTAR_ENOMEM, "q_lambda_bar_power: device allocation failed");
@@ -83,10 +94,61 @@ struct Power {
     // restrict qualifiers are formally violated by this call, harmlessly)
     cstar_status scale(double2 *y, double a) { return lin(0.0, y, a, y); }
     cstar_status copy(const double2 *x, double2 *y) {
+        if (x == y) return CSTAR_OK;
         CSTAR_HIP(hipMemcpyAsync(y, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
         return CSTAR_OK;
     }
 
+    // out = Q(m)^2 in, in the FP32 form `inner`, through tmp
+    cstar_status q2f(const float4 *in, float4 *tmp, float4 *out) {
+        const long st = n / 2 * (long)sizeof(float4);
+        ApplyArgs a{in, tmp, st, 1, 1, nullptr, m};
+        CSTAR_HIP(handle_apply(g, inner, a));
+        ApplyArgs b{tmp, out, st, 1, 1, nullptr, m};
+        CSTAR_HIP(handle_apply(g, inner, b));
+        applies_inner += 2;
+        return CSTAR_OK;
+    }
+    cstar_status dot32(const float4 *x, const float4 *y, double *out) {
+        CSTAR_HIP(launch_dot32(x, y, n / 2, partial, gout, s));
+        double2 h;
+        CSTAR_HIP(hipMemcpyAsync(&h, gout, sizeof(double2), hipMemcpyDeviceToHost, s));
+        CSTAR_HIP(hipStreamSynchronize(s));
+        *out = h.x;
+        return CSTAR_OK;
+    }
+    cstar_status lin32(float a, const float4 *x, float b, float4 *y) {
+        CSTAR_HIP(launch_lincomb32(2 * n, a, (const float *)x, b, (float *)y, 0.f, nullptr, s));
+        return CSTAR_OK;
+    }
+    // x = (Q^2)^-1 b as solve() below, in FP32 arithmetic on the FP32 form
+    // `inner` (b and x FP64, converted on the way in and out)
+    cstar_status solve32(const double2 *b, double2 *x, double tol, int maxit) {
+        const size_t bytes = (size_t)(n / 2) * sizeof(float4);
+        CSTAR_HIP(launch_to_f32(g->geo, 1, b, r32, s));
+        CSTAR_HIP(hipMemcpyAsync(p32, r32, bytes, hipMemcpyDeviceToDevice, s));
+        CSTAR_HIP(hipMemsetAsync(x32, 0, bytes, s));
+        cstar_status st;
+        double rr;
+        if ((st = dot32(r32, r32, &rr))) return st;
+        const double stop = tol * tol * rr;
+        solves++;
+        for (int it = 0; it < maxit && rr > stop; it++) {
+            if ((st = q2f(p32, tmp32, ap32))) return st;
+            double pap;
+            if ((st = dot32(p32, ap32, &pap))) return st;
+            if (!(pap > 0.0)) break;
+            const double a = rr / pap;
+            if ((st = lin32((float)a, p32, 1.f, x32)) || (st = lin32((float)-a, ap32, 1.f, r32))) return st;
+            double rn;
+            if ((st = dot32(r32, r32, &rn))) return st;
+            if ((st = lin32(1.f, r32, (float)(rn / rr), p32))) return st;
+            rr = rn;
+            cg_iterations++;
+        }
+        CSTAR_HIP(launch_to_f64(g->geo, 1, x32, x, s));
+        return CSTAR_OK;
+    }
     // x = (Q^2)^-1 b by CG from x = 0 to relative residual tol (at most maxit steps)
     cstar_status solve(const double2 *b, double2 *x, double2 *r, double2 *p, double2 *ap, double2 *tmp, double tol,
                        int maxit) {
@@ -111,6 +173,26 @@ struct Power {
             cg_iterations++;
         }
         return CSTAR_OK;
+    }
+    // the FP32 solve where the tolerance allows it.  FP32 CG's own residual
+    // can fall below the tolerance while the true one stalls near FP32
+    // rounding times the condition number of Q^2, so the solution's residual
+    // is recomputed in FP64; if it misses the tolerance by more than 10x, an
+    // FP64 solve of the correction finishes the job and every later solve is
+    // FP64.
+    cstar_status solve_any(const double2 *b, double2 *x, double2 *r, double2 *p, double2 *ap, double2 *tmp,
+                           double tol, int maxit) {
+        if (inner == CSTAR_FP64 || fp32_off || tol < 1e-6) return solve(b, x, r, p, ap, tmp, tol, maxit);
+        cstar_status st;
+        if ((st = solve32(b, x, tol, maxit))) return st;
+        double rr, bb;
+        if ((st = q2(x, tmp, ap)) || (st = copy(b, r)) || (st = lin(-1.0, ap, 1.0, r)) || (st = dot(r, r, &rr)) ||
+            (st = dot(b, b, &bb)))
+            return st;
+        if (rr <= 100.0 * tol * tol * bb) return CSTAR_OK;
+        fp32_off = true;
+        if ((st = solve(r, e, r, p, ap, tmp, std::min(1.0, tol * std::sqrt(bb / rr)), maxit))) return st;
+        return lin(1.0, e, 1.0, x);
     }
     // theta = v^H Q^2 v and r = |Q^2 v - theta v| for unit v (y, tmp: scratch)
     cstar_status residual(const double2 *v, double2 *y, double2 *tmp, double *theta, double *r) {
@@ -146,7 +228,8 @@ extern "C" cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const csta
     if (!g || !lambda_bar || !std::isfinite(m0)) return fail(CSTAR_EINVAL, "q_lambda_bar_power: bad argument");
     cstar_lbar_opts o{};
     if (opts_in) o = *opts_in;
-    if (!(o.tol >= 0.0) || o.degree < 0 || o.degree > 64 || o.plain_steps < 0 || o.max_outer < 0 || o.max_cg < 0)
+    if (!(o.tol >= 0.0) || o.degree < 0 || o.degree > 64 || o.plain_steps < 0 || o.max_outer < 0 || o.max_cg < 0 ||
+        (o.inner != CSTAR_FP64 && o.inner != CSTAR_FP32 && o.inner != CSTAR_FP32_BF16LINKS))
         return fail(CSTAR_EINVAL, "q_lambda_bar_power: bad options");
     const double tol = o.tol > 0.0 ? o.tol : 1e-3;
     const int deg = o.degree > 0 ? o.degree : 8;
@@ -156,7 +239,7 @@ extern "C" cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const csta
     const auto t0 = std::chrono::steady_clock::now();
     if (hipSetDevice(g->device) != hipSuccess) return fail(CSTAR_EDEVICE, "q_lambda_bar_power: hipSetDevice");
 
-    Power P{g, g->stream, m0, n_cplx(g->geo)};
+    Power P{g, g->stream, m0, n_cplx(g->geo), o.inner == CSTAR_FP64 ? CSTAR_FP64 : CSTAR_FP32};
     const size_t vb = sizeof(double2) * P.n;
     double2 *v, *x, *r, *p, *ap, *tmp, *y0, *y1;
     cstar_status st;
@@ -164,6 +247,11 @@ extern "C" cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const csta
         if ((st = P.alloc(b, vb))) return st;
     if ((st = P.alloc(&P.partial, gram_partial_bytes())) || (st = P.alloc(&P.gout, sizeof(double2) * 64)))
         return st;
+    if (P.inner != CSTAR_FP64) {
+        for (float4 **b : {&P.r32, &P.p32, &P.ap32, &P.tmp32, &P.x32})
+            if ((st = P.alloc(b, (size_t)(P.n / 2) * sizeof(float4)))) return st;
+        if ((st = P.alloc(&P.e, vb))) return st;
+    }
 
     CSTAR_HIP(launch_gauss(v, P.n, o.seed, P.s));
     if ((st = P.normalise(v))) return st;
@@ -176,15 +264,16 @@ extern "C" cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const csta
     while (!conv && outer < max_outer) {
         const double tin = std::max(1e-13, std::min(1e-3, 0.01 * rel));
         if (beta <= 0.0) {
-            if ((st = P.solve(v, x, r, p, ap, tmp, tin, max_cg)) || (st = P.copy(x, v))) return st;
+            if ((st = P.solve_any(v, x, r, p, ap, tmp, tin, max_cg)) || (st = P.copy(x, v))) return st;
         } else {
             // T_d(2B/beta - 1) v: y_1 = (2/beta) B v - v, y_{k+1} = (4/beta) B y_k - 2 y_k - y_{k-1},
             // the pair rescaled together after every step (only the direction matters)
-            if ((st = P.copy(v, y0)) || (st = P.solve(v, x, r, p, ap, tmp, tin, max_cg)) || (st = P.copy(x, y1)) ||
+            if ((st = P.copy(v, y0)) || (st = P.solve_any(v, x, r, p, ap, tmp, tin, max_cg)) || (st = P.copy(x, y1)) ||
                 (st = P.lin(-1.0, v, 2.0 / beta, y1)))
                 return st;
             for (int k = 1; k < deg; k++) {
-                if ((st = P.solve(y1, x, r, p, ap, tmp, tin, max_cg)) || (st = P.lin(4.0 / beta, x, -1.0, y0, -2.0, y1)))
+                if ((st = P.solve_any(y1, x, r, p, ap, tmp, tin, max_cg)) ||
+                    (st = P.lin(4.0 / beta, x, -1.0, y0, -2.0, y1)))
                     return st;
                 double nrm;
                 if ((st = P.normalise(y0, &nrm)) || (st = P.scale(y1, 1.0 / nrm))) return st;
@@ -216,6 +305,7 @@ extern "C" cstar_status q_lambda_bar_power(cstar_gauge *g, double m0, const csta
         stats->solves = P.solves;
         stats->cg_iterations = P.cg_iterations;
         stats->applies_fp64 = P.applies;
+        stats->applies_inner = P.applies_inner;
         stats->beta = beta;
         stats->resid_q2 = res;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -47,13 +47,14 @@ class EigStats(ctypes.Structure):
 
 class LbarOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("degree", ctypes.c_int), ("plain_steps", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+                ("max_outer", ctypes.c_int), ("max_cg", ctypes.c_int), ("seed", ctypes.c_ulonglong),
+                ("inner", ctypes.c_int)]
 
 
 class LbarStats(ctypes.Structure):
     _fields_ = [("outer", ctypes.c_int), ("solves", ctypes.c_int), ("cg_iterations", ctypes.c_long),
                 ("applies_fp64", ctypes.c_long), ("beta", ctypes.c_double), ("resid_q2", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("applies_inner", ctypes.c_long)]
 
 
 class WmassStats(ctypes.Structure):
@@ -295,10 +296,10 @@ class Gauge:
         return ev, res, st
 
     def lambda_bar_power(self, m0, tol=1e-3, degree=0, plain_steps=0, max_outer=0, max_cg=0, seed=1,
-                         raise_on_noconv=True):
+                         raise_on_noconv=True, inner=FP64):
         """min |lambda(Q(m0))| by the power method with Chebyshev acceleration on Q^-2:
         (lambda_bar, half-width bound, LbarStats)."""
-        o = LbarOpts(float(tol), int(degree), int(plain_steps), int(max_outer), int(max_cg), int(seed))
+        o = LbarOpts(float(tol), int(degree), int(plain_steps), int(max_outer), int(max_cg), int(seed), int(inner))
         lam = ctypes.c_double(0.0)
         bound = ctypes.c_double(0.0)
         st = LbarStats()

@@ -30,8 +30,9 @@ TINY = [
 ]
 
 
+@pytest.mark.parametrize("inner", [cstar.FP64, cstar.FP32_BF16LINKS])
 @pytest.mark.parametrize("case", TINY)
-def test_lambda_bar_power_matches_dense_oracle(case):
+def test_lambda_bar_power_matches_dense_oracle(case, inner):
     assert torch.cuda.is_available(), "GPU tests need a device"
     T, L, eps, seed, q, tbc, masses = case
     su3, th = synth.make_field(T, L, eps, seed)
@@ -40,23 +41,30 @@ def test_lambda_bar_power_matches_dense_oracle(case):
     for m in masses:
         print(f"lambda_bar power T={T} L={L} seed={seed} m={m}", flush=True)
         ref = float(np.min(np.abs(osign.pair_spectrum(op, m))))
-        lam, bound, st = g.lambda_bar_power(m, tol=1e-10, max_outer=2000)
+        lam, bound, st = g.lambda_bar_power(m, tol=1e-10, max_outer=2000, inner=inner)
         print(f"  lambda {lam:.15f} ref {ref:.15f} bound {bound:.2e} outer {st.outer} solves {st.solves} "
               f"cg {st.cg_iterations}")
         assert bound <= 1e-10 * lam
         assert abs(lam - ref) <= bound + DENSE_EPS
         assert lam >= ref - DENSE_EPS
-        assert st.applies_fp64 == 2 * (st.cg_iterations + st.outer + 1)
+        # two applies per CG iteration and per outer residual; an FP32 solve adds
+        # the two FP64 applies of its own residual check
+        if inner == cstar.FP64:
+            assert st.applies_fp64 == 2 * (st.cg_iterations + st.outer + 1) and st.applies_inner == 0
+        else:
+            assert st.applies_inner > 0
+            assert st.applies_fp64 + st.applies_inner >= 2 * (st.cg_iterations + st.outer + 1)
     g.close()
 
 
-def test_lambda_bar_power_agrees_with_block_solver_8_4():
+@pytest.mark.parametrize("inner", [cstar.FP64, cstar.FP32_BF16LINKS])
+def test_lambda_bar_power_agrees_with_block_solver_8_4(inner):
     """Smoothed 8^4 field of the batched workload's distribution at kappa 0.1365."""
     su3, th = synth.make_field(8, 8, 0.3, 2, smear_steps=10)
     g = cstar.Gauge(su3, th, 2 / 3)
     m = float(synth.kappa_to_m0(0.1365))
     ev, res, _ = g.lowest_eigs(m, 2, cstar.eig_opts(inner=cstar.FP64, tol=1e-10, max_iter=1000))
-    lam, bound, st = g.lambda_bar_power(m, tol=1e-3, max_outer=300)
+    lam, bound, st = g.lambda_bar_power(m, tol=1e-3, max_outer=300, inner=inner)
     print(f"8^4: power {lam:.10f} +- {bound:.2e} ({st.outer} outer, {st.solves} solves, {st.cg_iterations} CG, "
           f"{st.seconds:.2f} s); block solver {abs(ev[0]):.10f} +- {res[0]:.1e}")
     assert bound <= 1e-3 * lam
@@ -74,6 +82,8 @@ def test_lambda_bar_power_errors():
         g.lambda_bar_power(0.0, tol=-1.0)
     with pytest.raises(cstar.CstarError):
         g.lambda_bar_power(float("nan"))
+    with pytest.raises(cstar.CstarError):
+        g.lambda_bar_power(0.0, inner=7)
     # one outer step cannot reach 1e-14: ENOCONV, last iterate returned
     lam, bound, st = g.lambda_bar_power(0.0, tol=1e-14, max_outer=1, raise_on_noconv=False)
     assert st.outer == 1 and lam > 0.0 and bound > 1e-14 * lam
