@@ -761,8 +761,8 @@ def reweight_probe(args, w, su3_d, th_d, path):
     out["w_mass"] = {"n": 8, "range": [1e-2, 400.0], "delta": delta, "nsrc": 1, "tol": 1e-10, "log_w_mass": lwm,
                      "s": dt, "cg_iterations": st.cg_iterations, "eo_applies": st.eo_applies,
                      "ms_per_eo_apply": 1e3 * dt / max(1, st.eo_applies)}
-    log(f"[reweight] W_mass: log {lwm:.6e}, {dt:.1f} s, {st.cg_iterations} CG iterations, {st.eo_applies} FP64 "
-        f"even-odd applies ({out['w_mass']['ms_per_eo_apply']:.3f} ms each, all included)")
+    log(f"[reweight] W_mass: log {lwm:.6e}, {dt:.2f} s, {st.cg_iterations} CG iterations, {st.eo_applies} "
+        f"even-odd applies, FP32 and FP64 rows ({out['w_mass']['ms_per_eo_apply']:.3f} ms each, all included)")
     g.close()
     del eta
     lb_args = argparse.Namespace(**vars(args))

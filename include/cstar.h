@@ -312,17 +312,19 @@ cstar_status cstar_ratapprox_quartic(int n, double ra, double rb, double *A, dou
  *         - (D_hat_m' + i g5 mu_i)^{-1} dD (D_hat_m + i g5 nu_i)^{-1}
  * (nu_i = sqrt(nu2[i]), mu_i = sqrt(mu2[i])); the Gaussian average of
  * exp(-x_i) is det(1 + R_i)^{-1}, the i-th factor of W_mass.  Every inverse
- * is an FP64 conjugate-gradient solve of Q_hat^2 + s^2 to relative residual
- * tol followed by one Q_hat.  eta: device, nsrc FP64 even vectors (with
+ * is a solve of Q_hat^2 + s^2 to relative FP64 residual tol (iterative
+ * refinement: FP32 conjugate gradients on the FP32-row operator against the
+ * FP64 residual, FP64 CG if the refinement stops gaining) followed by one
+ * Q_hat.  eta: device, nsrc FP64 even vectors (with
  * density proportional to exp(-(eta, eta)) for the estimator).  expo: host
  * [n][nsrc], the x_il; log_w_mass: host, sum_i log((1/nsrc) sum_l exp(-x_il)).
- * stats: nullable.  Allocates 11 even vectors and a 64 MiB reduction buffer
- * and frees them before it returns.  Synchronous.
+ * stats: nullable.  Allocates 13 FP64 and 5 FP32 even vectors and a 64 MiB
+ * reduction buffer and frees them before it returns.  Synchronous.
  * Errors: EINVAL, ENOMEM, ENOCONV (a solve did not converge), EDEVICE.
  */
 typedef struct {
     long cg_iterations;  /* over all solves */
-    long eo_applies;     /* applications of D_hat or Q_hat */
+    long eo_applies;     /* applications of D_hat or Q_hat (FP64 or FP32 rows) */
     double seconds;
 } cstar_wmass_stats;
 cstar_status cstar_w_mass(cstar_gauge *g, double m, double m_prime, int n, const double *nu2, const double *mu2,

@@ -22,5 +22,8 @@ hipError_t launch_lincomb32(long nreal, float a, const float *x, float b, float 
                             hipStream_t s);
 hipError_t launch_to_f32(const Geo &g, int nvec, const double2 *src, float4 *dst, hipStream_t s);
 hipError_t launch_to_f64(const Geo &g, int nvec, const float4 *src, double2 *dst, hipStream_t s);
+// one even vector (parity-0 block) FP64 <-> FP32 native
+hipError_t launch_even_to_f32(const Geo &g, const double2 *src, float4 *dst, hipStream_t s);
+hipError_t launch_even_to_f64(const Geo &g, const float4 *src, double2 *dst, hipStream_t s);
 hipError_t launch_gauss(double2 *x, long n, unsigned long long seed, hipStream_t s);
 }  // namespace cstar

@@ -334,6 +334,39 @@ hipError_t launch_to_f32(const Geo &g, int nvec, const double2 *src, float4 *dst
                        nullptr);
     return hipGetLastError();
 }
+// the same conversion for one even vector (the parity-0 block alone):
+// FP64 double2 [12][Vh][2] <-> FP32 float4 [6][Vh][2]
+__global__ void k_convert_even(int Vh, const double2 *__restrict__ d, float4 *__restrict__ f, int to64,
+                               double2 *__restrict__ d_out, const float4 *__restrict__ f_in) {
+    const long total = 6L * Vh * 2;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int c = e & 1;
+        const long r = e >> 1;
+        const long h = r % Vh;
+        const int k2 = (int)(r / Vh);
+        const long i0 = ((long)(2 * k2) * Vh + h) * 2 + c;
+        const long i1 = ((long)(2 * k2 + 1) * Vh + h) * 2 + c;
+        const long i32 = ((long)k2 * Vh + h) * 2 + c;
+        if (!to64) {
+            const double2 a = d[i0], b = d[i1];
+            f[i32] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        } else {
+            const float4 q = f_in[i32];
+            d_out[i0] = make_double2(q.x, q.y);
+            d_out[i1] = make_double2(q.z, q.w);
+        }
+    }
+}
+
+hipError_t launch_even_to_f32(const Geo &g, const double2 *src, float4 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert_even, dim3(2048), dim3(256), 0, s, g.Vh, src, dst, 0, nullptr, nullptr);
+    return hipGetLastError();
+}
+hipError_t launch_even_to_f64(const Geo &g, const float4 *src, double2 *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_convert_even, dim3(2048), dim3(256), 0, s, g.Vh, nullptr, nullptr, 1, dst, src);
+    return hipGetLastError();
+}
+
 hipError_t launch_to_f64(const Geo &g, int nvec, const float4 *src, double2 *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_convert, dim3(4096), dim3(256), 0, s, 4L * g.Vh, g.Vh, nvec, nullptr, nullptr, 1, dst, src);
     return hipGetLastError();
