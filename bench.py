@@ -12,13 +12,15 @@ After the timed steps, on the same field: the single-RHS apply in every
 precision, the CPU oracle on a bounded sample, and the time to sign over the
 32-point kappa path for the mixed-precision, plain FP64 and learned forms,
 and for the mixed form in the paper's order (step A upward from the target
-with lambda_bar by the power method on Q^-2, then step B) --
+with lambda_bar by the power method on Q^-2, then step B); then the
+mass-reweighting rows (the even-odd apply, log W_eo, one W_mass estimate,
+lambda_bar by the power method, the ensemble driver on 16^4 fields) --
 each only while the wall-clock budget allows (skipped legs are named in the
 output).
 
 Printed: ONE JSON line -- RHS-applies/s of the block step, the roofline of
-its kernel (algorithmic bytes over the HIP-event launch time), the CPU oracle
-and the seconds per Pfaffian sign.
+its kernel (algorithmic bytes over the HIP-event launch time), the CPU oracle,
+the seconds per Pfaffian sign and the mass-reweighting measurements.
 """
 from __future__ import annotations
 
@@ -373,9 +375,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16, help="right-hand sides (and masses) of the block step")
     ap.add_argument("--budget-s", type=float, default=480.0,
                     help="wall-clock budget from process start; optional legs that would exceed it are skipped")
-    ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned,stepa",
-                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned, resid, stepa; "
-                         "'none')")
+    ap.add_argument("--legs", default="single,cpu,mixed,fp64,learned,stepa,reweight",
+                    help="legs after the timed steps (comma list of single, cpu, mixed, fp64, learned, resid, stepa, "
+                         "reweight; 'none')")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues (Kramers pairs) per mass point")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--block", type=int, default=0, help="eigensolver block size (0: 2k + max(8, k))")
@@ -607,6 +609,10 @@ def main():
         one_sign("mixed_step_a", "bf16", step_a=True)
     if len({v["signs"] for v in signs.values()}) > 1:
         log("[bench] WARNING: the forms disagree on the signs")
+    reweight = None
+    if "reweight" in legs and have(60, "reweight"):
+        # even-odd apply, W_eo, W_mass, lambda_bar by the power method, the ensemble driver
+        reweight = reweight_rows(args, w, su3_d, th_d, path)
 
     out = {
         "metric": "Dirac applies/s & HBM GB/s (% peak) at 32^4; s per Pfaffian sign, learned vs plain",
@@ -634,6 +640,7 @@ def main():
         "s_per_sign": {k_: v["s_per_sign"] for k_, v in signs.items()},
         "signs": signs,
         "signs_agree": len({v["signs"] for v in signs.values()}) <= 1,
+        "mass_reweighting": reweight,
         "skipped": skipped,
         "wall_s": time.time() - T_START,
     }
@@ -710,6 +717,11 @@ def eo_algorithmic_bytes(prec: int, nsites2: int, nrhs: int) -> float:
 
 
 def reweight_probe(args, w, su3_d, th_d, path):
+    """The mass-reweighting rows measured (reweight_rows), as one JSON line."""
+    print(json.dumps({"reweight_probe": reweight_rows(args, w, su3_d, th_d, path)}), flush=True)
+
+
+def reweight_rows(args, w, su3_d, th_d, path):
     """Measurements of the mass-reweighting rows at the workload's size: the
     even-odd apply (HIP events; bytes as eo_algorithmic_bytes), log W_eo, one
     W_mass estimate (one Gaussian source, order-8 rational approximation),
@@ -777,7 +789,7 @@ def reweight_probe(args, w, su3_d, th_d, path):
                        "status": int(st_e), "signs": signs.tolist(), "products": prods.tolist(),
                        "seconds": secs.tolist(), "s": time.perf_counter() - t0}
     log(f"[reweight] ensemble 2 x 2 at 16^4: signs {signs.tolist()}, {out['ensemble']['s']:.1f} s")
-    print(json.dumps({"reweight_probe": out}), flush=True)
+    return out
 
 
 def ensemble_probe(args, w):
