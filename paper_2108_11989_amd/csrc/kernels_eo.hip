@@ -232,16 +232,33 @@ __device__ __forceinline__ void herm_blocks_apply(const void *blk, const Geo &g,
 // One parity of D_hat for nrhs right-hand sides (stride between them in vector units).
 //  ODD  (parity 1 sites): chi = D_oo^{-1} (-1/2 H psi)        psi: parity-0 block of `a`, chi -> parity-1 block of `o`
 //  EVEN (parity 0 sites): out = (4+m+SW) psi + 1/2 H chi [g5]  psi: parity-0 block of `a`, chi: parity-1 block of `b`
+// One right-hand side: lane = site index of the parity.  Several: item =
+// (block of 256 sites, right-hand side), right-hand side fastest, and the
+// grid (a multiple of 8) is dealt so that every XCD (the hardware sends
+// workgroup w to XCD w mod 8) runs one contiguous range of items: the
+// workgroups of a block of sites for all right-hand sides run together on
+// one XCD, and the links, clover and inverse blocks of those sites are read
+// from its L2 after the first.  The arithmetic of a lane is the same either
+// way, so the bits are too.
 template <class Fmt, bool ODD>
 __global__ __launch_bounds__(256) void k_eo_half(Geo g, GaugeDev d, const typename Prec<Fmt>::V *__restrict__ a,
                                                  const typename Prec<Fmt>::V *__restrict__ b,
                                                  typename Prec<Fmt>::V *__restrict__ o, long stride_a, long stride_b,
                                                  long stride_o, int nrhs, double m, int gamma5, const void *inv) {
     using R = typename Prec<Fmt>::R;
-    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = (int)(gid / (2L * g.Vh));
-    if (j >= nrhs) return;
-    const int r = (int)(gid - (long)j * 2 * g.Vh);
+    const long nsite = 2L * g.Vh;
+    int j = 0;
+    long rl;
+    if (nrhs == 1) {
+        rl = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    } else {
+        const long w = blockIdx.x;
+        const long item = (w & 7) * (long)(gridDim.x >> 3) + (w >> 3);
+        j = (int)(item % nrhs);
+        rl = (item / nrhs) * 256 + threadIdx.x;
+    }
+    if (rl >= nsite) return;
+    const int r = (int)rl;
     const int c = r & 1;
     const int h = r >> 1;
     const int p = ODD ? 1 : 0;
@@ -343,8 +360,10 @@ hipError_t launch_logdet_ratio(const Geo &g, const GaugeDev &d, double m, double
 template <class Fmt>
 static void eo_launch(const Geo &g, const GaugeDev &d, const EoArgs &e, hipStream_t s) {
     using V = typename Prec<Fmt>::V;
-    const long lanes = 2L * g.Vh * e.nrhs;
-    const dim3 grd((unsigned)((lanes + 255) / 256)), blk(256);
+    // workgroups per right-hand side; several right-hand sides: a multiple of 8 (k_eo_half deals them by XCD)
+    const long per = (2L * g.Vh + 255) / 256;
+    const long nwg = e.nrhs == 1 ? per : (per * e.nrhs + 7) / 8 * 8;
+    const dim3 grd((unsigned)nwg), blk(256);
     const long sv = (long)sizeof(V);
     // odd half: chi (parity-1 block of tmp) from psi (parity-0 block of in)
     hipLaunchKernelGGL((k_eo_half<Fmt, true>), grd, blk, 0, s, g, d, (const V *)e.in, (const V *)nullptr,

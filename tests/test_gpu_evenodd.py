@@ -96,6 +96,32 @@ def test_dhat_fp32_forms_match_emulating_oracle(case, prec, mode):
     g.close()
 
 
+@pytest.mark.parametrize("shape", [(6, 4, 5), (6, 8, 3)])
+@pytest.mark.parametrize("prec", [cstar.FP64, cstar.FP32, cstar.FP32_BF16LINKS])
+def test_dhat_multi_rhs_equals_single_launches_bitwise(shape, prec):
+    """A launch of several right-hand sides deals its workgroups by (block of
+    sites, right-hand side) instead of site order; every lane's arithmetic is
+    that of the single-vector launch, so each right-hand side must come out
+    bit for bit as its own launch.  6x4^3 has 384 sites of the doubled
+    lattice per parity (a ragged second block of 256), and neither 2 x 5
+    nor 12 x 3 workgroups is a multiple of 8."""
+    T, L, nrhs = shape
+    print(f"eo multi-RHS T={T} L={L} nrhs={nrhs} prec={prec}", flush=True)
+    su3, th = synth.make_field(T, L, 0.4, 21)
+    g = cstar.Gauge(su3, th, -1 / 3, synth.CSW_SU3, synth.CSW_U1)
+    n = g.new_native(1, prec).numel() // 2  # elements of one even vector (half a native spinor)
+    ev = g.new_native(nrhs, prec)[: nrhs * n].clone()
+    ev.normal_(generator=torch.Generator(device="cuda").manual_seed(5))
+    out = torch.empty_like(ev)
+    g.eo_apply(ev, out, 0.1, prec, True, nrhs)
+    for j in range(nrhs):
+        one = torch.empty_like(ev[:n])
+        g.eo_apply(ev[j * n:(j + 1) * n].clone(), one, 0.1, prec, True, 1)
+        assert torch.equal(out[j * n:(j + 1) * n], one), j
+    torch.cuda.synchronize()
+    g.close()
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_log_w_eo_matches_oracle(case):
     T, L, eps, seed, q, tbc = case
